@@ -1,0 +1,429 @@
+"""Checks that pin the CPU oracle to facts fixed outside it.
+
+Each check takes an oracle library handle (the normal build or a deliberately
+broken copy) and raises AssertionError when the oracle disagrees with:
+  - closed forms: a constant slab composites to 1-(1-a)^n, an affine field
+    seen along an axis gives a finite product known without any grid access;
+  - the paper's worked functor chains (Sec. 3.3) and the dimension changes
+    of Tab. 'functors';
+  - ray/box geometry special cases and the pixel count of an axis projection;
+  - an independent brute-force per-sample loop on tiny grids;
+  - the bound that early termination at theta moves a channel by at most 1-theta.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+import oracle
+from oracle import brute
+from scenes import Camera, Scene, make_source
+from scenes import configs, fields
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _img(rec, sc):
+    return rec["rgba"].reshape(sc.height, sc.width, 4)
+
+
+def _cnt(rec, sc):
+    return rec["samples"].reshape(sc.height, sc.width)
+
+
+# ---------------------------------------------------------------------------
+# P1: constant slab
+# ---------------------------------------------------------------------------
+
+def _slab_scene(L=8, a=0.1, rgb=(0.2, 0.6, 0.9), weight=1.0, interpolation=0, guard=0, step=0.5,
+                ert=1.0, clip=(), extra_sources=()):
+    dims = (L, 6, 5)
+    # the paper's analytic example source is 42 everywhere; add(-41.5) brings it into [0,1]
+    src = make_source("const42", fields.constant(dims, guard, 42.0), guard=guard, chain="add(-41.5)",
+                      weight=weight, tf=configs.constant_tf(rgb, a))
+    cam = configs.axis_camera(dims, axis=0, width=9, height=7, ortho_height=9.0)
+    return Scene(dims=dims, sources=[src, *extra_sources], camera=cam, width=9, height=7, step=step,
+                 interpolation=interpolation, clip=list(clip), ert_threshold=ert)
+
+
+def _hit_mask(sc):
+    """Pixels of the axis camera whose ray runs through the box (pixel centres strictly inside)."""
+    cam = sc.camera
+    h = cam.ortho_height / 2.0
+    mask = np.zeros((sc.height, sc.width), dtype=bool)
+    for j in range(sc.height):
+        for i in range(sc.width):
+            x = (2.0 * (i + 0.5) / sc.width - 1.0) * h * sc.width / sc.height
+            y = (1.0 - 2.0 * (j + 0.5) / sc.height) * h
+            # axis 0 camera: right = fwd x up = (1,0,0)x(0,0,1) = (0,-1,0), up' = (0,0,1)
+            py = cam.center[1] - x
+            pz = cam.center[2] + y
+            mask[j, i] = 0.0 < py < sc.dims[1] and 0.0 < pz < sc.dims[2]
+    return mask
+
+
+def pin_constant_slab(lib):
+    for interp, guard in ((0, 0), (1, 0), (1, 1)):
+        sc = _slab_scene(interpolation=interp, guard=guard)
+        rec = oracle.render(sc, lib=lib)
+        img, cnt = _img(rec, sc), _cnt(rec, sc)
+        hit = _hit_mask(sc)
+        assert hit.sum() > 10 and (~hit).sum() > 4
+        n = 16                                    # L / step
+        A = 1.0 - (1.0 - 0.1) ** n
+        assert np.all(cnt[hit] == n), (interp, guard, cnt)
+        assert np.all(cnt[~hit] == 0)
+        assert np.allclose(img[hit][:, 3], A, rtol=0, atol=1e-12)
+        assert np.allclose(img[hit][:, :3], np.array([0.2, 0.6, 0.9]) * A, rtol=0, atol=1e-12)
+        assert np.all(img[~hit] == 0.0)
+
+
+def pin_constant_slab_weight_and_two_sources(lib):
+    dims = (8, 6, 5)
+    second = make_source("const42b", fields.constant(dims, 0, 42.0), guard=0, chain="add(-41.5)",
+                         weight=0.5, tf=configs.constant_tf((1.0, 0.0, 0.25), 0.3))
+    sc = _slab_scene(weight=0.8, extra_sources=[second])
+    rec = oracle.render(sc, lib=lib)
+    img = _img(rec, sc)
+    hit = _hit_mask(sc)
+    S = 0.8 * 0.1 + 0.5 * 0.3
+    E = 0.8 * 0.1 * np.array([0.2, 0.6, 0.9]) + 0.5 * 0.3 * np.array([1.0, 0.0, 0.25])
+    A = 1.0 - (1.0 - S) ** 16
+    assert np.allclose(img[hit][:, 3], A, atol=1e-12)
+    assert np.allclose(img[hit][:, :3], E / S * A, atol=1e-12)
+    # a disabled source contributes nothing (and is never read: give it a NULL-free poisoned layout)
+    second.enabled = False
+    rec2 = oracle.render(sc, lib=lib)
+    ref = oracle.render(_slab_scene(weight=0.8), lib=lib)
+    assert np.array_equal(rec2["rgba"], ref["rgba"])
+    # weight 0 is the same as the source being absent
+    second.enabled = True
+    second.weight = 0.0
+    rec3 = oracle.render(sc, lib=lib)
+    assert np.allclose(rec3["rgba"], ref["rgba"], atol=1e-15)
+
+
+def pin_mix_saturation(lib):
+    """Sources whose weighted opacities sum past 1 are rescaled to opacity 1."""
+    dims = (8, 6, 5)
+    second = make_source("b", fields.constant(dims, 0, 42.0), guard=0, chain="add(-41.5)", weight=1.0,
+                         tf=configs.constant_tf((1.0, 0.0, 0.0), 0.9))
+    sc = _slab_scene(a=0.6, rgb=(0.0, 0.0, 1.0), extra_sources=[second])
+    rec = oracle.render(sc, lib=lib)
+    img, cnt = _img(rec, sc), _cnt(rec, sc)
+    hit = _hit_mask(sc)
+    S = 0.6 + 0.9
+    E = (0.6 * np.array([0.0, 0.0, 1.0]) + 0.9 * np.array([1.0, 0.0, 0.0])) / S
+    assert np.allclose(img[hit][:, 3], 1.0, atol=1e-12)
+    assert np.allclose(img[hit][:, :3], E, atol=1e-12)
+    assert np.all(cnt[hit] == 1)                   # opacity 1 after the first sample meets theta = 1
+
+
+def pin_constant_slab_ert(lib):
+    sc = _slab_scene(L=40, ert=0.999)
+    rec = oracle.render(sc, lib=lib)
+    img, cnt = _img(rec, sc), _cnt(rec, sc)
+    hit = _hit_mask(sc)
+    n_star = math.ceil(math.log(0.001) / math.log(0.9))
+    assert n_star == 66
+    assert np.all(cnt[hit] == n_star), np.unique(cnt[hit])
+    assert np.allclose(img[hit][:, 3], 1.0 - 0.9 ** n_star, atol=1e-12)
+
+
+def pin_constant_slab_clip(lib):
+    # keep x >= 3.1: samples at x = (k+1/2)/2 >= 3.1 are k = 6..15
+    sc = _slab_scene(clip=[(1.0, 0.0, 0.0, -3.1)])
+    rec = oracle.render(sc, lib=lib)
+    cnt = _cnt(rec, sc)
+    hit = _hit_mask(sc)
+    n_kept = sum(1 for k in range(16) if (k + 0.5) * 0.5 >= 3.1)
+    assert n_kept == 10
+    assert np.all(cnt[hit] == n_kept)
+    assert np.allclose(_img(rec, sc)[hit][:, 3], 1.0 - 0.9 ** n_kept, atol=1e-12)
+    # a scaled normal describes the same half-space; the opposite plane keeps the rest
+    sc2 = _slab_scene(clip=[(2.0, 0.0, 0.0, -6.2)])
+    assert np.array_equal(oracle.render(sc2, lib=lib)["samples"], rec["samples"])
+    sc3 = _slab_scene(clip=[(-1.0, 0.0, 0.0, 3.1)])
+    assert np.all(_cnt(oracle.render(sc3, lib=lib), sc3)[hit] == 16 - n_kept)
+
+
+# ---------------------------------------------------------------------------
+# P2: linear ramp
+# ---------------------------------------------------------------------------
+
+def _ramp_scene(axis, sign, guard, L=12, alpha=0.0625, beta=0.03125, a_max=0.375, step=0.5):
+    dims = [5, 6, 7]
+    dims[axis] = L
+    dims = tuple(dims)
+    src = make_source("ramp", fields.ramp(dims, guard, alpha, beta, axis), guard=guard,
+                      tf=configs.linear_alpha_tf((0.3, 0.5, 0.7), a_max))
+    cam = configs.axis_camera(dims, axis=axis, sign=sign, width=6, height=6, ortho_height=4.0)
+    return Scene(dims=dims, sources=[src], camera=cam, width=6, height=6, step=step, interpolation=1,
+                 ert_threshold=1.0)
+
+
+def pin_linear_ramp(lib):
+    for axis in (0, 1, 2):
+        for sign in (1.0, -1.0):
+            for guard in (1, 0):
+                L, alpha, beta, a_max = 12, 0.0625, 0.03125, 0.375   # exact in float32 storage
+                sc = _ramp_scene(axis, sign, guard, L, alpha, beta, a_max)
+                rec = oracle.render(sc, lib=lib)
+                img, cnt = _img(rec, sc), _cnt(rec, sc)
+                n = int(L / 0.5)
+                # positions along the axis: the ray enters at 0 (sign +) or at L (sign -)
+                ps = [(k + 0.5) * 0.5 if sign > 0 else L - (k + 0.5) * 0.5 for k in range(n)]
+                if guard == 0:                     # clamp-to-edge within half a cell of each face
+                    ps = [min(max(p, 0.5), L - 0.5) for p in ps]
+                T, A = 1.0, 0.0
+                for p in ps:
+                    s = a_max * min(max(alpha * p + beta, 0.0), 1.0)
+                    A = A + T * s
+                    T = T * (1.0 - s)
+                A_closed = 1.0 - np.prod([1.0 - a_max * min(max(alpha * p + beta, 0.0), 1.0) for p in ps])
+                assert abs(A - A_closed) < 1e-14
+                assert np.all(cnt == n), (axis, sign, guard, np.unique(cnt))
+                assert np.allclose(img[..., 3], A_closed, rtol=0, atol=1e-12), (axis, sign, guard)
+                assert np.allclose(img[..., :3], np.array([0.3, 0.5, 0.7]) * A_closed, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P3: functor chains
+# ---------------------------------------------------------------------------
+
+def pin_functor_examples(lib):
+    with open(os.path.join(GOLDEN, "functor_examples.json")) as f:
+        g = json.load(f)
+    for ex in g["examples"]:
+        for case in ex["cases"]:
+            v, _ = oracle.chain_eval(ex["chain"], ex["f_dim"], case["in"], lib=lib)
+            assert abs(v - case["out"]) < 1e-12, (ex["id"], case, v)
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        x, y, z = rng.uniform(-3, 3, size=3)
+        v, d = oracle.chain_eval("mul(2,3,4) | add(1) | length", 3, [x, y, z], lib=lib)
+        assert d == 1
+        assert abs(v - math.sqrt((2 * x + 1) ** 2 + (3 * y + 1) ** 2 + (4 * z + 1) ** 2)) < 1e-12
+        v, _ = oracle.chain_eval("mul(0,1,0) | sum", 3, [x, y, z], lib=lib)
+        assert abs(v - y) < 1e-15
+        v, _ = oracle.chain_eval("pow(2) | sum | pow(0.5)", 3, [x, y, z], lib=lib)
+        assert abs(v - math.sqrt(x * x + y * y + z * z)) < 1e-12
+        w = rng.uniform(0.1, 4.0)
+        v, _ = oracle.chain_eval("pow(3) | pow(0.5)", 1, [w], lib=lib)
+        assert abs(v - w ** 1.5) < 1e-12
+        v, _ = oracle.chain_eval("", 4, [x, y, z, 1.0], lib=lib)
+        assert v == x
+    for case in g["dimension_changes"]["cases"]:
+        _, d = oracle.chain_eval(case["chain"], case["f_dim"], [0.5] * case["f_dim"], lib=lib)
+        assert d == case["dim"], case
+    for bad, f_dim in (("foo", 1), ("add(1,2)", 3), ("length(2)", 3), ("add()", 1), ("mul(1) |", 1),
+                       ("add(1 2)", 1), ("sum | add(1,2)", 2), (" | ".join(["add(1)"] * 9), 1),
+                       ("add(1,2,3,4,5)", 4), ("length", 5)):
+        try:
+            oracle.chain_eval(bad, f_dim, [0.0] * 4, lib=lib)
+        except ValueError:
+            continue
+        raise AssertionError(f"chain {bad!r} accepted")
+
+
+def pin_chain_render_equivalence(lib):
+    """mul(2) | pow(0.5) on f renders like the identity chain on sqrt(2 f) (nearest sampling)."""
+    rng = np.random.default_rng(11)
+    dims = (6, 7, 5)
+    f = fields.uniform_random(rng, dims, 0, 1, 0.0, 0.4).astype(np.float64)
+    tf = configs.random_tf(rng, 5, 0.5)
+    cam = configs.orbit_camera(dims, (0.3, -1.0, 0.5), distance_factor=1.5, fovy_deg=50.0)
+    a = make_source("f", f.astype(np.float32), guard=0, chain="mul(2) | pow(0.5)", tf=tf)
+    b = make_source("g", np.sqrt(2.0 * a.values[..., 0]).astype(np.float32), guard=0, tf=tf)
+    sa = Scene(dims=dims, sources=[a], camera=cam, width=11, height=9, interpolation=0)
+    sb = sa.with_(sources=[b])
+    ra, rb = oracle.render(sa, lib=lib), oracle.render(sb, lib=lib)
+    assert np.array_equal(ra["samples"], rb["samples"])
+    # sqrt(2f) stored as float32 differs from the chain's FP64 value by < 2^-24 relative
+    assert np.allclose(ra["rgba"], rb["rgba"], atol=1e-6)
+    assert ra["rgba"][:, 3].max() > 0.05
+
+
+# ---------------------------------------------------------------------------
+# P2b: transfer table
+# ---------------------------------------------------------------------------
+
+def pin_tf_table(lib):
+    t = oracle.tf_table([(0.0, 0.1, 0.2, 0.3, 0.0), (1.0, 0.9, 0.7, 0.5, 1.0)], lib=lib)
+    j = np.arange(256) / 255.0
+    lin = np.stack([0.1 + 0.8 * j, 0.2 + 0.5 * j, 0.3 + 0.2 * j, j], axis=1)
+    assert np.allclose(t, lin, atol=1e-15)
+    pts = [(0.0, 0, 0, 0, 0), (51 / 255, 1.0, 0.5, 0.25, 0.125), (200 / 255, 0.0, 1.0, 0.0, 1.0), (1.0, 1, 1, 1, 1)]
+    t = oracle.tf_table(pts, lib=lib)
+    assert np.allclose(t[51], [1.0, 0.5, 0.25, 0.125], atol=1e-15)
+    assert np.allclose(t[200], [0.0, 1.0, 0.0, 1.0], atol=1e-15)
+    assert np.allclose(t[0], 0.0) and np.allclose(t[255], 1.0)
+    w = 51.0 / 149.0                     # x = 102/255 lies 51/149 of the way from 51/255 to 200/255
+    assert np.allclose(t[102], [1.0 - w, 0.5 + 0.5 * w, 0.25 - 0.25 * w, 0.125 + 0.875 * w], atol=1e-15)
+    # halfway between two control points the table is their mean
+    mid = oracle.tf_table([(0.0, 0, 0, 0, 0), (2 / 255, 1.0, 1.0, 1.0, 1.0), (1.0, 1, 1, 1, 1)], lib=lib)
+    assert np.allclose(mid[1], 0.5, atol=1e-15)
+    for bad in ([(0.0, 0, 0, 0, 0)], [(0.1, 0, 0, 0, 0), (1.0, 0, 0, 0, 0)], [(0.0, 0, 0, 0, 0), (0.9, 0, 0, 0, 0)],
+                [(0.0, 0, 0, 0, 0), (0.5, 0, 0, 0, 0), (0.5, 0, 0, 0, 0), (1.0, 0, 0, 0, 0)],
+                [(0.0, 0, 0, 0, 1.5), (1.0, 0, 0, 0, 0)]):
+        try:
+            oracle.tf_table(bad, lib=lib)
+        except ValueError:
+            continue
+        raise AssertionError(f"transfer function {bad} accepted")
+
+
+def pin_classification_lookup(lib):
+    """A linear-alpha table classifies a constant value v to alpha = v (a slab of one sample)."""
+    for v in (0.0, 0.2, 0.5, 0.73, 1.0, 1.7, -0.3):
+        dims = (1, 3, 3)
+        src = make_source("c", fields.constant(dims, 0, v), guard=0,
+                          tf=configs.linear_alpha_tf((1.0, 1.0, 1.0), 1.0))
+        cam = configs.axis_camera(dims, axis=0, width=3, height=3, ortho_height=3.0)
+        sc = Scene(dims=dims, sources=[src], camera=cam, width=3, height=3, step=1.0, interpolation=0,
+                   ert_threshold=1.0)
+        rec = oracle.render(sc, lib=lib)
+        centre = _img(rec, sc)[1, 1]
+        assert _cnt(rec, sc)[1, 1] == 1
+        assert abs(centre[3] - min(max(float(np.float32(v)), 0.0), 1.0)) < 1e-12, (v, centre)
+
+
+# ---------------------------------------------------------------------------
+# P5: geometry
+# ---------------------------------------------------------------------------
+
+def pin_geometry(lib):
+    # axis projection: the number of hit pixels is the count of pixel centres over the box face
+    dims = (5, 7, 3)
+    src = make_source("c", fields.constant(dims, 0, 0.5), guard=0, tf=configs.constant_tf((1, 1, 1), 0.2))
+    cam = configs.axis_camera(dims, axis=2, width=16, height=12, ortho_height=10.0)
+    sc = Scene(dims=dims, sources=[src], camera=cam, width=16, height=12, step=0.5, interpolation=0)
+    rec = oracle.render(sc, lib=lib)
+    cnt = _cnt(rec, sc)
+    spacing = 10.0 / 12
+    # axis 2 camera: fwd=(0,0,1), up=(0,1,0): right = fwd x up = (-1,0,0), up' = (0,1,0)
+    cols = [i for i in range(16) if 0 < dims[0] / 2 - (i + 0.5 - 8) * spacing < dims[0]]
+    rows = [j for j in range(12) if 0 < dims[1] / 2 + (6 - j - 0.5) * spacing < dims[1]]
+    assert (cnt > 0).sum() == len(cols) * len(rows)
+    assert np.all(cnt[np.ix_(rows, cols)] == int(dims[2] / 0.5))
+    # eye inside the box: every ray hits, starts at t0 = 0 and leaves where the nearest face is
+    cube = (8, 8, 8)
+    src = make_source("c", fields.constant(cube, 0, 0.5), guard=0, tf=configs.constant_tf((1, 1, 1), 0.01))
+    cam = Camera(eye=(4.0, 4.0, 4.0), center=(10.0, 5.0, 4.5), up=(0.0, 0.0, 1.0), fovy_deg=90.0)
+    sc = Scene(dims=cube, sources=[src], camera=cam, width=7, height=5, step=0.5, interpolation=0,
+               ert_threshold=1.0)
+    rec = oracle.render(sc, lib=lib)
+    for j in range(5):
+        for i in range(7):
+            hit, o, d, t0, t1 = oracle.ray(sc, i, j, lib=lib)
+            assert hit and t0 == 0.0 and abs(np.linalg.norm(d) - 1.0) < 1e-14
+            t_exit = min(4.0 / abs(c) for c in d if c != 0.0)
+            assert abs(t1 - t_exit) < 1e-12
+            n = sum(1 for k in range(100) if (k + 0.5) * 0.5 < t_exit)
+            assert rec["samples"][j * 7 + i] == n
+    # a ray parallel to a face and outside it misses; on the face plane it hits
+    dims = (4, 4, 4)
+    src = make_source("c", fields.constant(dims, 0, 0.5), guard=0, tf=configs.constant_tf((1, 1, 1), 0.2))
+    for y, expect in ((4.5, False), (4.0, True), (-0.01, False), (2.0, True)):
+        cam = Camera(eye=(-5.0, y, 2.0), center=(0.0, y, 2.0), up=(0.0, 0.0, 1.0), projection="orthographic",
+                     ortho_height=1.0)
+        sc = Scene(dims=dims, sources=[src], camera=cam, width=1, height=1, step=0.5, interpolation=0)
+        hit, o, d, t0, t1 = oracle.ray(sc, 0, 0, lib=lib)
+        assert hit == expect, (y, hit)
+        assert (oracle.render(sc, lib=lib)["samples"][0] > 0) == expect
+    # a perspective camera behind the box looking away sees nothing
+    cam = Camera(eye=(-3.0, 2.0, 2.0), center=(-10.0, 2.0, 2.0), up=(0.0, 0.0, 1.0), fovy_deg=40.0)
+    sc = Scene(dims=dims, sources=[src], camera=cam, width=6, height=6, step=0.5, interpolation=0)
+    assert np.all(oracle.render(sc, lib=lib)["rgba"] == 0.0)
+
+
+def pin_orientation(lib):
+    """Row 0 is the top of the image and the camera's right is fwd x up."""
+    dims = (8, 8, 8)
+    v = np.zeros((8, 8, 8), dtype=np.float32)
+    v[6:, 0:2, :] = 1.0          # high z, low y: [z][y][x]
+    src = make_source("o", v, guard=0, tf=configs.linear_alpha_tf((1, 1, 1), 0.5))
+    # looking along +x with up +z: right = (1,0,0) x (0,0,1) = (0,-1,0), so low y is on the right
+    cam = configs.axis_camera(dims, axis=0, width=8, height=8, ortho_height=8.0)
+    sc = Scene(dims=dims, sources=[src], camera=cam, width=8, height=8, step=0.5, interpolation=0)
+    img = _img(oracle.render(sc, lib=lib), sc)
+    lit = img[..., 3] > 0
+    assert lit[:2, 6:].all() and not lit[2:, :].any() and not lit[:, :6].any(), lit.astype(int)
+
+
+def pin_perspective_symmetry(lib):
+    """A field mirror-symmetric in y, seen from a camera on the mirror plane, gives a mirrored image."""
+    rng = np.random.default_rng(5)
+    dims = (7, 6, 5)
+    half = fields.uniform_random(rng, (7, 3, 5), 0, 1, 0.0, 1.0)
+    v = np.concatenate([half, half[:, ::-1, :]], axis=1)
+    src = make_source("m", v, guard=0, tf=configs.random_tf(rng, 4, 0.4))
+    cam = Camera(eye=(-9.0, 3.0, 7.0), center=(3.5, 3.0, 2.5), up=(0.0, 0.0, 1.0), fovy_deg=45.0)
+    for interp in (0, 1):
+        sc = Scene(dims=dims, sources=[src], camera=cam, width=10, height=7, step=0.4, interpolation=interp)
+        img = _img(oracle.render(sc, lib=lib), sc)
+        assert img[..., 3].max() > 0.05
+        assert np.allclose(img, img[:, ::-1], atol=1e-9), interp
+
+
+# ---------------------------------------------------------------------------
+# P4: brute force; P6: early-termination bound
+# ---------------------------------------------------------------------------
+
+def pin_brute_force(lib, seeds=range(40)):
+    for seed in seeds:
+        sc = configs.random_small_scene(seed)
+        rec = oracle.render(sc, lib=lib)
+        img, cnt = brute.render(sc)
+        assert np.array_equal(_cnt(rec, sc), np.array(cnt)), seed
+        assert np.allclose(_img(rec, sc), np.array(img), rtol=0, atol=1e-12, equal_nan=False), seed
+
+
+def pin_ert_bound(lib):
+    for seed in range(6):
+        sc = configs.random_small_scene(100 + seed)
+        for s in sc.sources:
+            s.tf = [(x, r, g, b, min(1.0, 4 * a)) for (x, r, g, b, a) in s.tf]
+        full = oracle.render(sc, lib=lib, ert_threshold=1.0)["rgba"]
+        for theta in (0.999, 0.99, 0.9):
+            cut = oracle.render(sc, lib=lib, ert_threshold=theta)["rgba"]
+            assert np.all(np.abs(cut - full) <= (1.0 - theta) + 1e-12), (seed, theta)
+
+
+def pin_fp16_bf16_reads(lib):
+    """Values exactly representable in FP16 and BF16 render identically from either storage."""
+    rng = np.random.default_rng(9)
+    dims = (5, 4, 6)
+    v = (rng.integers(0, 64, size=(6 + 2, 4 + 2, 5 + 2, 3)) / 64.0).astype(np.float32)
+    tf = configs.random_tf(rng, 5, 0.6)
+    base = make_source("v", v, guard=1, chain="length | mul(0.6)", tf=tf)
+    cam = configs.orbit_camera(dims, (1.0, -0.4, 0.7), 1.4, 50.0)
+    sc = Scene(dims=dims, sources=[base], camera=cam, width=9, height=8, interpolation=1)
+    ref = oracle.render(sc, lib=lib)
+    assert ref["rgba"][:, 3].max() > 0.05
+    for dt in ("f16", "bf16"):
+        s = make_source("v", v, dtype=dt, guard=1, chain="length | mul(0.6)", tf=tf)
+        assert np.array_equal(s.values, base.values)
+        r = oracle.render(sc.with_(sources=[s]), lib=lib)
+        assert np.array_equal(r["rgba"], ref["rgba"]), dt
+    # and a value that needs the exponent/mantissa split right: 1.5 * 2^-3 and 3 * 2^4
+    for val in (0.1875, 48.0, 2.0 ** -20):
+        for dt in ("f16", "bf16"):
+            s = make_source("c", fields.constant((1, 1, 1), 0, val), dtype=dt, guard=0, chain="mul(0.01)",
+                            tf=configs.linear_alpha_tf((1, 1, 1), 1.0))
+            cam = configs.axis_camera((1, 1, 1), axis=0, width=1, height=1, ortho_height=0.5)
+            sc1 = Scene(dims=(1, 1, 1), sources=[s], camera=cam, width=1, height=1, step=1.0,
+                        interpolation=0, ert_threshold=1.0)
+            a = oracle.render(sc1, lib=lib)["rgba"][0, 3]
+            assert abs(a - min(val * 0.01, 1.0)) < 1e-12, (val, dt, a)
+
+
+ALL_PINS = [pin_constant_slab, pin_constant_slab_weight_and_two_sources, pin_mix_saturation,
+            pin_constant_slab_ert, pin_constant_slab_clip, pin_linear_ramp, pin_functor_examples,
+            pin_chain_render_equivalence, pin_tf_table, pin_classification_lookup, pin_geometry,
+            pin_orientation, pin_perspective_symmetry, pin_brute_force, pin_ert_bound,
+            pin_fp16_bf16_reads]

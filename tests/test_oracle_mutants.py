@@ -1,0 +1,106 @@
+"""Plant plausible mistakes in a copy of the oracle and check that a pin catches each.
+
+Every mutant is one textual change to oracle/isaac_oracle.c (a dropped term, a
+wrong sign, an off-by-one, a transposed operand ...).  The copy is compiled
+to a temporary library and the full pin suite runs against it in a child
+process (a mutant may also crash, which counts as caught).  A mutant that
+passes every pin means the pins do not constrain that part of the oracle.
+"""
+
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "isaac_oracle.c")
+
+MUTANTS = [
+    ("composite_drops_transmittance", "C[c] = C[c] + (1.0 - A) * E[c];", "C[c] = C[c] + E[c];"),
+    ("alpha_drops_transmittance", "A = A + (1.0 - A) * S;", "A = A + S;"),
+    ("grid_not_half_step", "t0 + ((double)k + 0.5) * sc->step", "t0 + ((double)k) * sc->step"),
+    ("trilinear_vertex_centred", "double u = p[a] - 0.5;", "double u = p[a];"),
+    ("trilinear_weights_swapped", "w *= bit ? f[a] : 1.0 - f[a];", "w *= bit ? 1.0 - f[a] : f[a];"),
+    ("chain_last_component", "    return v[0];\n}", "    return v[dim - 1];\n}"),
+    ("add_no_broadcast", "v[k] = v[k] + (f->nargs == 1 ? f->arg[0] : f->arg[k]);", "v[k] = v[k] + f->arg[k];"),
+    ("mul_no_broadcast", "v[k] = v[k] * (f->nargs == 1 ? f->arg[0] : f->arg[k]);", "v[k] = v[k] * f->arg[k];"),
+    ("pow_operands_swapped", "pow(v[k], f->nargs == 1 ? f->arg[0] : f->arg[k])",
+     "pow(f->nargs == 1 ? f->arg[0] : f->arg[k], v[k])"),
+    ("length_without_square", "s += v[k] * v[k];", "s += v[k] * v[k] * v[k];"),
+    ("sum_of_squares", "for (int k = 0; k < dim; k++) s += v[k];\n", "for (int k = 0; k < dim; k++) s += v[k] * v[k];\n"),
+    ("tf_scale_256", "double u = 255.0 * t;", "double u = 256.0 * t;"),
+    ("tf_no_lerp", "rgba[c] = table[4 * j + c] + f * (table[4 * (j + 1) + c] - table[4 * j + c]);",
+     "rgba[c] = table[4 * j + c];"),
+    ("tf_index_cap", "if (j > 254) j = 254;", "if (j > 253) j = 253;"),
+    ("nan_not_zero", "double t = isnan(x) ? 0.0 :", "double t = isnan(x) ? 1.0 :"),
+    ("pl_wrong_weight", "double w = (x - x0) / (x1 - x0);", "double w = (x - x0) / x1;"),
+    ("mix_no_saturation", "if (sumS > 1.0) {", "if (sumS > 2.0) {"),
+    ("mix_not_renormalised", "sumE[c] /= sumS;", "sumE[c] /= 1.0;"),
+    ("weight_dropped", "double wa = src->weight * rgba[3];", "double wa = rgba[3];"),
+    ("clip_side_flipped", "if (s < 0.0) keep = 0;", "if (s > 0.0) keep = 0;"),
+    ("eye_inside_not_clamped", "if (lo < 0.0) lo = 0.0;", "if (lo < -1e300) lo = 0.0;"),
+    ("camera_left_handed", "cross3(P->fwd, sc->up, P->right);", "cross3(sc->up, P->fwd, P->right);"),
+    ("image_upside_down", "double y = (1.0 - 2.0 * (j + 0.5) / sc->height) * P->h;",
+     "double y = (2.0 * (j + 0.5) / sc->height - 1.0) * P->h;"),
+    ("no_aspect", "* P->h * P->aspect;", "* P->h;"),
+    ("fovy_not_halved", "tan(0.5 * sc->fovy_deg * ORACLE_PI / 180.0)", "tan(sc->fovy_deg * ORACLE_PI / 180.0)"),
+    ("ortho_origin_fixed", "o[a] = sc->eye[a] + x * P->right[a] + y * P->upp[a];", "o[a] = sc->eye[a];"),
+    ("strides_transposed", "(int64_t)x * s->stride[0] + (int64_t)y * s->stride[1]",
+     "(int64_t)x * s->stride[1] + (int64_t)y * s->stride[0]"),
+    ("guard_ignored", "if (src->guard < 1) q[a] = clamp_int(", "if (src->guard < 2) q[a] = clamp_int("),
+    ("disabled_read", "        if (!src->enabled) continue;                  /* never read */\n", ""),
+    ("ert_strict", "if (A >= sc->ert_threshold) {", "if (A > sc->ert_threshold + 1e-3) {"),
+    ("nearest_rounds", "clamp_int((int)floor(p[a]), 0, sc->dims[a] - 1);\n            x = source_value",
+     "clamp_int((int)floor(p[a] + 0.5), 0, sc->dims[a] - 1);\n            x = source_value"),
+    ("half_exponent_bias", "e - 25);", "e - 24);"),
+    ("bf16_shift", "(uint32_t)b << 16;", "(uint32_t)b << 15;"),
+    ("parallel_slab_open", "if (o[a] < 0.0 || o[a] > n) return 0;", "if (o[a] < 0.0) return 0;"),
+    ("exit_inclusive", "int inside = t < t1;", "int inside = t <= t1 + 0.25;"),
+]
+
+CHILD = r"""
+import sys
+sys.path[:0] = [{root!r}, {tests!r}]
+import oracle, pins
+lib = oracle.load({lib!r})
+for pin in pins.ALL_PINS:
+    try:
+        pin(lib)
+    except (AssertionError, ValueError) as e:
+        print("CAUGHT", pin.__name__)
+        sys.exit(0)
+print("SURVIVED")
+sys.exit(3)
+"""
+
+
+def _run_mutant(tmp, name, find, repl):
+    src = open(SRC).read()
+    assert src.count(find) == 1, f"mutation site of {name} not unique/absent"
+    path = os.path.join(tmp, f"{name}.c")
+    with open(path, "w") as f:
+        f.write(src.replace(find, repl))
+    lib = os.path.join(tmp, f"lib{name}.so")
+    subprocess.run(["gcc", "-std=c11", "-D_DEFAULT_SOURCE", "-O1", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I", os.path.join(ROOT, "oracle"), "-o", lib, path, "-lm"], check=True)
+    code = CHILD.format(root=ROOT, tests=os.path.join(ROOT, "tests"), lib=lib)
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    return name, p.returncode, (p.stdout + p.stderr)[-400:]
+
+
+@pytest.mark.slow
+def test_every_mutant_is_caught():
+    with tempfile.TemporaryDirectory() as tmp:
+        with ThreadPoolExecutor(max_workers=max(1, min(6, os.cpu_count() or 1))) as ex:
+            results = list(ex.map(lambda m: _run_mutant(tmp, *m), MUTANTS))
+    survived = [(n, out) for n, rc, out in results if rc == 3]
+    assert not survived, "mutants not caught by any pin: " + "; ".join(n for n, _ in survived)
+
+
+def test_mutation_sites_exist():
+    src = open(SRC).read()
+    for name, find, _ in MUTANTS:
+        assert src.count(find) == 1, name
