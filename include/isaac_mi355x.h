@@ -1,0 +1,220 @@
+/*
+ * isaac_mi355x.h -- C ABI of an MI355X (gfx950) volume ray caster for in situ
+ * visualization of simulation fields.
+ *
+ * The operations follow Matthes et al., "In situ, steerable, hardware-
+ * independent and data-structure agnostic visualization with ISAAC"
+ * (arXiv:1611.09048):
+ *   - sources: scalar or vector fields (feature dimension 1..4) assigned to
+ *     every regularly spaced position of the local volume, read in place
+ *     through an accessor that handles alignment, pitch and axis order, with
+ *     optional guard (ghost) cells and a persistent flag (Sec. 3.1, 3.2 and
+ *     the listing "Definition of a source in ISAAC");
+ *   - functor chains "f | g | ..." of add, mul, length, sum, pow applied to a
+ *     date right after it is read (Sec. 3.3, Tab. "functors");
+ *   - free transfer functions, clipping planes and data interpolation
+ *     (Sec. 3, feature list);
+ *   - one render call that takes control and returns an image (Sec. 3.2).
+ *
+ * Conventions shared by every call
+ *   Coordinates: index space of the local volume.  Voxel (x,y,z) occupies
+ *     [x,x+1]x[y,y+1]x[z,z+1]; its value sits at the cell centre; the local
+ *     box is [0,Nx]x[0,Ny]x[0,Nz].
+ *   Pointers: "device" pointers are HIP device addresses on the context's
+ *     device; "host" pointers are ordinary process memory.
+ *   Ownership: the library never writes to source memory and never frees
+ *     memory it did not allocate.  Strings and arrays passed in are copied
+ *     before the call returns unless stated otherwise.
+ *   Errors: every call returns ISAAC_OK (0) or a negative isaac_status and
+ *     never throws or aborts.  A failing set_* call changes nothing.  A
+ *     render validates every job before launching any.  A device fault is
+ *     reported as ISAAC_ERR_DEVICE, which is sticky: destroy the context.
+ *     isaac_last_error() holds a message for the last failure.
+ *   Threads: a context is used by one host thread at a time.
+ */
+#ifndef ISAAC_MI355X_H
+#define ISAAC_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISAAC_MAX_SOURCES 8      /* sources per volume */
+#define ISAAC_MAX_FUNCTORS 8     /* functors per chain */
+#define ISAAC_MAX_CLIP 8         /* clipping planes per render */
+#define ISAAC_TF_ENTRIES 256     /* transfer table resolution */
+#define ISAAC_MAX_BATCH 256      /* jobs per isaac_render call */
+
+typedef int32_t isaac_status;
+enum {
+    ISAAC_OK = 0,
+    ISAAC_ERR_INVALID_ARGUMENT = -1,
+    ISAAC_ERR_BAD_FUNCTOR = -2,      /* functor chain does not parse or has the wrong arity */
+    ISAAC_ERR_BAD_TRANSFER = -3,     /* transfer-function points invalid */
+    ISAAC_ERR_OUT_OF_MEMORY = -4,
+    ISAAC_ERR_BUSY = -5,             /* serving: no slot or memory free right now */
+    ISAAC_ERR_NOT_FOUND = -6,        /* unknown volume, handle or ticket */
+    ISAAC_ERR_DEVICE = -7            /* HIP error; sticky */
+};
+
+typedef enum { ISAAC_F32 = 0, ISAAC_F16 = 1, ISAAC_BF16 = 2 } isaac_dtype;
+enum { ISAAC_PERSPECTIVE = 0, ISAAC_ORTHOGRAPHIC = 1 };
+enum { ISAAC_NEAREST = 0, ISAAC_TRILINEAR = 1 };
+
+/* isaac_render flags */
+#define ISAAC_ASYNC 1u       /* enqueue on the context stream and return without waiting */
+#define ISAAC_TIMING 2u      /* bracket the ray-casting kernel with HIP events (isaac_timing) */
+#define ISAAC_NO_GRAPH 4u    /* batched renders: launch directly instead of replaying a hipGraph */
+
+typedef struct isaac_context isaac_context;   /* opaque */
+
+typedef struct {
+    int device;                  /* HIP device ordinal */
+    void* stream;                /* hipStream_t to enqueue on (borrowed, never destroyed); NULL: own stream */
+    size_t mem_budget_bytes;     /* serving: device bytes for library-owned output images; 0: 1 GiB */
+    int max_inflight;            /* serving: outstanding submitted requests; 0: 64 */
+    int max_volumes;             /* volume ids 0..max_volumes-1; 0: 256 */
+} isaac_init_desc;
+
+/* Create a context on a device.  *out receives the context, or NULL on error
+ * (use isaac_init_error() for the message then). */
+isaac_status isaac_init(const isaac_init_desc* desc, isaac_context** out);
+
+/* Wait for queued work and release everything the library allocated. */
+void isaac_destroy(isaac_context* ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char* isaac_last_error(const isaac_context* ctx);
+
+/* Message of the last failed isaac_init in this process. */
+const char* isaac_init_error(void);
+
+/*
+ * Source descriptor (the source concept: feature dimension, guard and
+ * persistence flags, name, update callback and accessor; Sec. 3.2).
+ *
+ * The accessor is a device address per component of interior voxel (0,0,0)
+ * and a signed byte stride per axis, so interleaved (AoS) or separate (SoA)
+ * components, padded rows, any axis order and reversed axes are all read in
+ * place.  Voxel (x,y,z) component c is at comp[c] + x*stride[0] +
+ * y*stride[1] + z*stride[2] for x in [-guard, Nx-1+guard] and likewise in y, z.
+ */
+typedef struct {
+    const char* name;                 /* copied; may be NULL */
+    int f_dim;                        /* feature dimension, 1..4 */
+    isaac_dtype dtype;                /* storage type; arithmetic is FP32 */
+    const void* comp[4];              /* device; BORROWED, never written */
+    int64_t stride[3];                /* bytes along x, y, z */
+    int guard;                        /* guard layers present in memory (0: border clamped under interpolation) */
+    int persistent;                   /* 0: the library copies the field after update() into its own buffer */
+    const char* functor_chain;        /* e.g. "mul(2,3,4) | add(1) | length"; NULL or "": identity */
+    float weight;                     /* in [0,1]: scales the source's opacity when sources are combined */
+    int enabled;                      /* 0: never read */
+    void (*update)(void* user, int enabled, void* pointer);   /* called before each render; may be NULL */
+    void* user;                       /* first argument of update */
+} isaac_source_desc;
+
+/* Define (or redefine) volume `volume_id`: its size in cells and its sources.
+ * Chains are parsed here (ISAAC_ERR_BAD_FUNCTOR on error).  Every source
+ * keeps its current transfer function if the new source count covers it,
+ * otherwise it starts with an opacity-0 table until isaac_set_transfer.
+ * Must not be called while renders of this volume are in flight. */
+isaac_status isaac_set_sources(isaac_context* ctx, int volume_id, const int32_t dims[3],
+                               const isaac_source_desc* src, int n_src);
+
+/* Piecewise-linear RGBA transfer function over the classification domain
+ * [0,1]: x strictly increasing from 0 to 1, every value in [0,1].  It is
+ * tabulated at 256 points j/255 and looked up with linear interpolation; a
+ * value outside [0,1] is clamped, NaN maps to 0. */
+typedef struct { double x; double rgba[4]; } isaac_tf_point;
+
+/* Bake and upload a table, make it the current table of (volume, source) and
+ * return its handle (>= 0) in *out_handle (may be NULL).  Handles stay valid
+ * until isaac_release_transfer. */
+isaac_status isaac_set_transfer(isaac_context* ctx, int volume_id, int source,
+                                const isaac_tf_point* pts, int n_pts, int32_t* out_handle);
+
+/* Give a table back; its slot is reused once no queued render refers to it.
+ * Releasing a source's current table leaves it current until replaced. */
+isaac_status isaac_release_transfer(isaac_context* ctx, int32_t handle);
+
+typedef struct { double n[3]; double d; } isaac_clip_plane;   /* keep points with n.x + d >= 0 */
+
+typedef struct {
+    int volume_id;
+    int width, height;                /* image size in pixels, >= 1 */
+    int projection;                   /* ISAAC_PERSPECTIVE or ISAAC_ORTHOGRAPHIC */
+    double eye[3], center[3], up[3];  /* camera, index-space units; right = forward x up */
+    double fovy_deg;                  /* perspective: vertical field of view, (0,180) */
+    double ortho_height;              /* orthographic: image height in voxels, > 0 */
+    double step;                      /* sample spacing along the ray in voxels, > 0 */
+    int interpolation;                /* ISAAC_NEAREST or ISAAC_TRILINEAR */
+    int n_clip;                       /* <= ISAAC_MAX_CLIP */
+    const isaac_clip_plane* clip;     /* host; copied */
+    const int32_t* tf_handles;        /* host, one per source; NULL: the current tables */
+    const float* weights;             /* host, one per source; NULL: descriptor weights */
+    const int32_t* enabled;           /* host, one per source; NULL: descriptor flags */
+    float ert_threshold;              /* stop a ray once opacity >= this; 0: 0.999; > 1: never */
+    float* out_rgba;                  /* device, CALLER-OWNED, height*width*4 floats, premultiplied, row 0 = top */
+    int32_t* out_samples;             /* device or NULL: per-pixel count of composited samples */
+    void* update_pointer;             /* passed as `pointer` to every source's update() */
+} isaac_render_desc;
+
+/* Ray-cast jobs (all validated before any launch).  One job is one kernel
+ * launch over its image; several jobs form one persistent launch over a
+ * shared tile queue, replayed as a hipGraph unless ISAAC_NO_GRAPH.  Without
+ * ISAAC_ASYNC the call returns after the images are complete. */
+isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags);
+
+/* Sum and count of the kernel durations of ISAAC_TIMING renders since the
+ * last call (waits for them), then resets. */
+isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count);
+
+/* Ray-tile shape for jobs of a given image-size class (autotuner output).
+ * size_class = ceil(log2(max(width,height))) clamped to [0,15]; wave_w in
+ * {8,16,32,64} (rays of one 64-wide wave are wave_w x 64/wave_w pixels);
+ * waves_x in {1,2,4} (a 4-wave workgroup is waves_x x 4/waves_x waves);
+ * unroll in {1,2,4}: samples per early-termination check. */
+isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w, int waves_x, int unroll);
+isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_w, int* waves_x, int* unroll);
+
+/* ---- serving: library-owned output images admitted against mem_budget ---- */
+
+/* Enqueue one render into a library-owned image (job->out_rgba and
+ * job->out_samples are ignored).  Returns ISAAC_ERR_BUSY when max_inflight
+ * requests are outstanding or the image does not fit the memory budget. */
+isaac_status isaac_submit(isaac_context* ctx, const isaac_render_desc* job, uint64_t* out_ticket);
+
+/* Several requests as one batched launch; tickets[i] receives job i's ticket.
+ * All or nothing: ISAAC_ERR_BUSY if any of them would not be admitted. */
+isaac_status isaac_submit_batch(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs,
+                                uint64_t* tickets);
+
+/* *done = 1 once the image is complete; *out_rgba then points at it (device,
+ * owned by the library until isaac_release). */
+isaac_status isaac_poll(isaac_context* ctx, uint64_t ticket, int* done, const float** out_rgba);
+
+/* Return the image memory of a completed (or not yet complete: waits) ticket. */
+isaac_status isaac_release(isaac_context* ctx, uint64_t ticket);
+
+/* Bytes of the serving memory budget in use / in total. */
+isaac_status isaac_serving_usage(isaac_context* ctx, size_t* used, size_t* budget, int* inflight);
+
+/* ---- host-only helpers (no device needed) ---- */
+
+/* Parse a functor chain for an f_dim-component source: *out_dim receives the
+ * dimension of the chain's result, *out_ops the number of functors after
+ * host-side simplification.  Message in err on ISAAC_ERR_BAD_FUNCTOR. */
+isaac_status isaac_check_functor_chain(const char* chain, int f_dim, int* out_dim, int* out_ops,
+                                       char* err, int errlen);
+
+/* Library version string. */
+const char* isaac_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

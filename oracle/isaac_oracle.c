@@ -438,7 +438,7 @@ static void render_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
     if (!box_interval(P, o, d, &t0, &t1)) return;
     double C[3] = {0.0, 0.0, 0.0}, A = 0.0;
     double allowance = 0.0;
-    int flags = 0;
+    int flags = 0, kinds = 0;
     const double delta = sc->delta;
     for (int64_t k = 0;; k++) {
         double t = t0 + ((double)k + 0.5) * sc->step;
@@ -456,22 +456,27 @@ static void render_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
             if (fabs(s) < delta * nn) near_plane = 1;
         }
         int near_exit = (t1 - t < delta) && (t - t1 < delta);
+        int kind = (near_plane ? ORACLE_FLAG_CLIP : 0) | (near_exit ? ORACLE_FLAG_EXIT : 0);
         double T = 1.0 - A;                          /* transmittance before this point */
         if (!keep) {
-            if (near_exit || near_plane) {           /* the other side might keep it */
+            if (kind) {                              /* the other side might keep it */
                 double E[3], S;
                 scan_point(P, p, NULL, E, &S);
                 allowance += T * max_abs_diff(E, S, (double[3]){0, 0, 0}, 0.0);
                 flags++;
+                kinds |= kind;
+                px->count_slack++;
             }
             if (!inside) break;
             continue;
         }
         double E[3], S;
         scan_point(P, p, NULL, E, &S);
-        if (near_exit || near_plane) {               /* the other side might drop it */
+        if (kind) {                                  /* the other side might drop it */
             allowance += T * max_abs_diff(E, S, (double[3]){0, 0, 0}, 0.0);
             flags++;
+            kinds |= kind;
+            px->count_slack++;
         }
         if (sc->interpolation == 0) {
             int cell[3], alt[3], mask = nearest_flags(P, p, cell, alt);
@@ -488,6 +493,7 @@ static void render_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
                 }
                 allowance += T * worst;
                 flags++;
+                kinds |= ORACLE_FLAG_NEAREST;
             }
         }
         /* classical front-to-back compositing */
@@ -498,18 +504,21 @@ static void render_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
             if (A - sc->ert_threshold < sc->ert_margin) {  /* the other side might go on */
                 allowance += 1.0 - A;
                 flags++;
+                kinds |= ORACLE_FLAG_ERT;
             }
             break;
         }
         if (sc->ert_threshold - A < sc->ert_margin) {      /* the other side might stop here */
             allowance += 1.0 - A;
             flags++;
+            kinds |= ORACLE_FLAG_ERT;
         }
     }
     for (int c = 0; c < 3; c++) px->rgba[c] = C[c];
     px->rgba[3] = A;
     px->allowance = allowance;
     px->flags = flags;
+    px->kinds = kinds;
 }
 
 static int check_scene(const oracle_scene* sc, char* err, int errlen) {

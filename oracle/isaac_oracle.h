@@ -57,7 +57,7 @@ typedef struct {
     int interpolation;                /* 0 nearest, 1 trilinear */
     int n_clip;
     const double* clip;               /* n_clip * 4: nx ny nz d, keep n.x + d >= 0 */
-    double ert_threshold;             /* stop once accumulated opacity >= this */
+    double ert_threshold;             /* stop once accumulated opacity >= this (> 1: never) */
     double delta;                     /* decision margin for the flip allowance (voxels) */
     double ert_margin;                /* opacity margin for the flip allowance at the threshold */
 } oracle_scene;
@@ -67,8 +67,12 @@ typedef struct {
     int64_t samples;                  /* scan points composited */
     double allowance;                 /* per-channel bound on what a flipped decision can change */
     int32_t flags;                    /* decisions taken within the margin */
+    int32_t kinds;                    /* ORACLE_FLAG_* bits of those decisions */
+    int32_t count_slack;              /* how far the sample count may move (clip plane and box exit) */
     int32_t pad;
 } oracle_pixel;
+
+enum { ORACLE_FLAG_NEAREST = 1, ORACLE_FLAG_CLIP = 2, ORACLE_FLAG_EXIT = 4, ORACLE_FLAG_ERT = 8 };
 
 /* Render pixels [first, first+count) of the row-major image (row 0 at the top).
  * Returns 0, or -1 with a message in err. */

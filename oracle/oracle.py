@@ -40,8 +40,10 @@ class _Scene(ctypes.Structure):
 
 
 PIXEL_DTYPE = np.dtype([("rgba", np.float64, 4), ("samples", np.int64), ("allowance", np.float64),
-                        ("flags", np.int32), ("pad", np.int32)])
-assert PIXEL_DTYPE.itemsize == 56
+                        ("flags", np.int32), ("kinds", np.int32), ("count_slack", np.int32), ("pad", np.int32)])
+assert PIXEL_DTYPE.itemsize == 64
+FLAG_NEAREST, FLAG_CLIP, FLAG_EXIT, FLAG_ERT = 1, 2, 4, 8
+NO_TERMINATION = 2.0        # a threshold opacity never reaches
 
 DELTA = 2.0 ** -12          # voxels: decisions closer than this may go either way on the GPU
 ERT_MARGIN = 1e-4           # opacity margin around the termination threshold

@@ -1,0 +1,1162 @@
+// Host runtime of the ray caster: the C ABI declared in include/isaac_mi355x.h.
+//
+// Responsibilities: validating descriptors (all-or-nothing), compiling
+// functor chains to bytecode, baking transfer tables, building per-job
+// parameter blocks (camera basis in FP64, clip planes, active sources),
+// staging them through pinned memory, launching the kernels of raycast.hip,
+// batching jobs into persistent launches replayed as hipGraphs, and the
+// library-owned output images of the serving calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cctype>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/isaac_mi355x.h"
+#include "isaac_internal.h"
+
+using namespace isaac;
+
+namespace {
+
+constexpr int kRingSlots = 16;
+constexpr int kTfSlots = 4096;      // transfer tables resident at once (16 MiB)
+constexpr double kPi = 3.14159265358979323846;
+
+struct Status {
+    isaac_status code = ISAAC_OK;
+    std::string msg;
+};
+
+// ---------------------------------------------------------------------------
+// functor chains: "name(args) | name | ..." (Sec. 3.3, Tab. "functors")
+// ---------------------------------------------------------------------------
+struct CompiledChain {
+    int n_ops = 0;
+    int out_dim = 1;
+    DevOp ops[kMaxOps];
+};
+
+bool compile_chain(const char* text, int f_dim, CompiledChain& out, std::string& err) {
+    out = CompiledChain();
+    if (f_dim < 1 || f_dim > 4) {
+        err = "f_dim must be 1..4";
+        return false;
+    }
+    int dim = f_dim;
+    std::vector<DevOp> ops;
+    const char* s = text ? text : "";
+    auto ws = [&]() { while (*s == ' ' || *s == '\t' || *s == '\n' || *s == '\r') ++s; };
+    ws();
+    int parsed = 0;
+    while (*s) {
+        if (parsed > 0) {
+            if (*s != '|') {
+                err = std::string("expected '|' before: ") + s;
+                return false;
+            }
+            ++s;
+            ws();
+        }
+        std::string name;
+        while (*s && std::isalpha((unsigned char)*s)) name.push_back(*s++);
+        ws();
+        std::vector<double> args;
+        bool parens = false;
+        if (*s == '(') {
+            parens = true;
+            ++s;
+            ws();
+            while (*s != ')') {
+                char* end = nullptr;
+                double v = std::strtod(s, &end);
+                if (end == s) {
+                    err = "expected a number in the arguments of '" + name + "'";
+                    return false;
+                }
+                args.push_back(v);
+                s = end;
+                ws();
+                if (*s == ',') {
+                    ++s;
+                    ws();
+                    if (*s == ')') {
+                        err = "dangling ',' in '" + name + "'";
+                        return false;
+                    }
+                } else if (*s != ')') {
+                    err = "expected ',' or ')' in '" + name + "'";
+                    return false;
+                }
+            }
+            ++s;
+            ws();
+        }
+        (void)parens;
+        DevOp op{};
+        op.dim = dim;
+        if (name == "add" || name == "mul" || name == "pow") {
+            if (args.size() != 1 && (int)args.size() != dim) {
+                err = "'" + name + "' takes 1 or " + std::to_string(dim) + " arguments, got " +
+                      std::to_string(args.size());
+                return false;
+            }
+            op.kind = name == "add" ? OP_ADD : name == "mul" ? OP_MUL : OP_POW;
+            for (int c = 0; c < 4; ++c) op.arg[c] = (float)(args.size() == 1 ? args[0] : (c < dim ? args[c] : 0.0));
+        } else if (name == "length" || name == "sum") {
+            if (!args.empty()) {
+                err = "'" + name + "' takes no arguments";
+                return false;
+            }
+            op.kind = name == "length" ? OP_LENGTH : OP_SUM;
+            dim = 1;
+        } else {
+            err = name.empty() ? std::string("expected a functor name before: ") + s
+                               : "unknown functor '" + name + "'";
+            return false;
+        }
+        ops.push_back(op);
+        ++parsed;
+        if (parsed > kMaxOps) {
+            err = "more than " + std::to_string(kMaxOps) + " functors";
+            return false;
+        }
+    }
+    // host-side simplification; every rewrite is exact in IEEE arithmetic
+    // except pow(x, 0.5) -> sqrt(x), which differs only for -0 and -inf
+    std::vector<DevOp> simp;
+    for (const DevOp& op : ops) {
+        bool all_eq = true;
+        for (int c = 1; c < op.dim; ++c) all_eq = all_eq && op.arg[c] == op.arg[0];
+        if ((op.kind == OP_MUL || op.kind == OP_POW) && all_eq && op.arg[0] == 1.0f) continue;
+        if (op.kind == OP_ADD && all_eq && op.arg[0] == 0.0f) continue;
+        DevOp o = op;
+        if (op.kind == OP_POW && all_eq && op.arg[0] == 0.5f) o.kind = OP_SQRT;
+        if (op.kind == OP_POW && all_eq && op.arg[0] == 2.0f) o.kind = OP_SQUARE;
+        simp.push_back(o);
+    }
+    out.n_ops = (int)simp.size();
+    for (int i = 0; i < out.n_ops; ++i) out.ops[i] = simp[i];
+    out.out_dim = dim;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// transfer tables: T[j] = PL(j / 255), j = 0..255
+// ---------------------------------------------------------------------------
+bool bake_tf(const isaac_tf_point* pts, int n, float* table, std::string& err) {
+    if (!pts || n < 2) {
+        err = "a transfer function needs at least 2 points";
+        return false;
+    }
+    if (pts[0].x != 0.0 || pts[n - 1].x != 1.0) {
+        err = "transfer function points must start at x=0 and end at x=1";
+        return false;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (i > 0 && !(pts[i].x > pts[i - 1].x)) {
+            err = "transfer function x must increase strictly";
+            return false;
+        }
+        for (int c = 0; c < 4; ++c)
+            if (!(pts[i].rgba[c] >= 0.0 && pts[i].rgba[c] <= 1.0)) {
+                err = "transfer function values must lie in [0,1]";
+                return false;
+            }
+    }
+    int seg = 0;
+    for (int j = 0; j < kTfEntries; ++j) {
+        const double x = (double)j / 255.0;
+        while (seg < n - 2 && x > pts[seg + 1].x) ++seg;
+        const isaac_tf_point& a = pts[seg];
+        const isaac_tf_point& b = pts[seg + 1];
+        const double w = (x - a.x) / (b.x - a.x);
+        for (int c = 0; c < 4; ++c) table[4 * j + c] = (float)(a.rgba[c] + w * (b.rgba[c] - a.rgba[c]));
+    }
+    return true;
+}
+
+int esize_of(int dtype) { return dtype == ISAAC_F32 ? 4 : 2; }
+
+// ---------------------------------------------------------------------------
+// context state
+// ---------------------------------------------------------------------------
+struct SourceHost {
+    isaac_source_desc desc{};
+    std::string name, chain_text;
+    CompiledChain chain;
+    int reach = 0;                  // guard layers the kernel may read (0 or 1)
+    // readable ranges of the user's memory
+    uint64_t base[4] = {0, 0, 0, 0};
+    uint32_t num_records[4] = {0, 0, 0, 0};
+    int32_t comp_off[4] = {0, 0, 0, 0};
+    int32_t stride[3] = {0, 0, 0};
+    int packed = 0;
+    // shadow copy for non-persistent sources
+    void* shadow = nullptr;
+    size_t shadow_bytes = 0;
+};
+
+struct Volume {
+    bool defined = false;
+    int32_t dims[3] = {0, 0, 0};
+    std::vector<SourceHost> src;
+    std::vector<int32_t> tf;        // current table handle per source
+};
+
+struct TfSlot {
+    bool live = false;              // allocated (referenced by a handle)
+    bool released = false;
+    uint64_t last_use = 0;          // render sequence number that last read it
+};
+
+struct RingSlot {
+    DevJob* host = nullptr;         // pinned
+    DevJob* dev = nullptr;
+    int* cursor = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    // graph cache
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int g_jobs = -1, g_tiles = -1, g_grid = -1, g_src = -1;
+};
+
+struct Pending {
+    uint64_t seq;
+    hipEvent_t ev;
+};
+
+struct Ticket {
+    uint64_t id;
+    float* out = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool done = false;
+};
+
+struct TileShape {
+    int wave_w = 8, waves_x = 2, unroll = 1;
+};
+
+}  // namespace
+
+struct isaac_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipStream_t> serve_streams;
+    int serve_rr = 0;
+    int n_cu = 0;
+    int blocks_per_cu = 1;
+    size_t budget = 0, used = 0;
+    int max_inflight = 64;
+    std::vector<Volume> volumes;
+    // transfer-table pool
+    float* tf_pool = nullptr;
+    int tf_capacity = 0;
+    std::vector<TfSlot> tf_slots;
+    // job staging ring
+    RingSlot ring[kRingSlots];
+    int ring_next = 0;
+    // completion tracking
+    uint64_t seq = 0, completed = 0;
+    std::deque<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    // timing
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
+    // serving
+    std::map<uint64_t, Ticket> tickets;
+    std::multimap<size_t, float*> image_cache;
+    size_t cached = 0;
+    uint64_t next_ticket = 1;
+    TileShape shapes[16];
+    std::string last_error;
+    bool sticky = false;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+isaac_status set_err(isaac_context* ctx, isaac_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) {
+        ctx->last_error = buf;
+        if (code == ISAAC_ERR_DEVICE) ctx->sticky = true;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return set_err(ctx, ISAAC_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+hipEvent_t get_event(isaac_context* ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void put_event(isaac_context* ctx, hipEvent_t e) {
+    if (e) ctx->event_pool.push_back(e);
+}
+
+bool is_current(const isaac_context* ctx, int32_t slot);
+
+// Retire finished renders; reclaim released tables no queued render reads.
+void update_completed(isaac_context* ctx) {
+    while (!ctx->pending.empty()) {
+        Pending& p = ctx->pending.front();
+        if (hipEventQuery(p.ev) != hipSuccess) break;
+        ctx->completed = p.seq;
+        put_event(ctx, p.ev);
+        ctx->pending.pop_front();
+    }
+    for (size_t i = 0; i < ctx->tf_slots.size(); ++i) {
+        TfSlot& s = ctx->tf_slots[i];
+        if (s.live && s.released && s.last_use <= ctx->completed && !is_current(ctx, (int32_t)i)) s = TfSlot();
+    }
+}
+
+isaac_status check_ctx(isaac_context* ctx) {
+    if (!ctx) return ISAAC_ERR_INVALID_ARGUMENT;
+    if (ctx->sticky) return ISAAC_ERR_DEVICE;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    return ISAAC_OK;
+}
+
+bool is_current(const isaac_context* ctx, int32_t slot) {
+    for (const Volume& v : ctx->volumes)
+        for (int32_t t : v.tf)
+            if (t == slot) return true;
+    return false;
+}
+
+// Allocate a slot and upload a table.  Slot 0 is the all-zero table.  A
+// reclaimed slot is no longer read by any queued render, so the synchronous
+// upload cannot race with a kernel.
+isaac_status new_tf_slot(isaac_context* ctx, const float* table, int32_t* handle) {
+    update_completed(ctx);
+    int slot = -1;
+    for (int i = 1; i < ctx->tf_capacity; ++i)
+        if (!ctx->tf_slots[i].live) {
+            slot = i;
+            break;
+        }
+    if (slot < 0)
+        return set_err(ctx, ISAAC_ERR_OUT_OF_MEMORY, "all %d transfer tables are live; release some", ctx->tf_capacity);
+    HIP_TRY(ctx, hipMemcpy(ctx->tf_pool + (size_t)slot * kTfEntries * 4, table, kTfEntries * 4 * sizeof(float),
+                           hipMemcpyHostToDevice));
+    ctx->tf_slots[slot] = TfSlot();
+    ctx->tf_slots[slot].live = true;
+    *handle = slot;
+    return ISAAC_OK;
+}
+
+// Byte ranges the kernel may read for one source: one range per component,
+// or a single range when the components are interleaved (packed).
+isaac_status derive_layout(isaac_context* ctx, const int32_t dims[3], SourceHost& s) {
+    const isaac_source_desc& d = s.desc;
+    const int es = esize_of(d.dtype);
+    s.reach = d.guard >= 1 ? 1 : 0;
+    int64_t mn = 0, mx = 0;   // reachable voxel offsets relative to voxel (0,0,0)
+    for (int a = 0; a < 3; ++a) {
+        const int64_t e0 = -(int64_t)s.reach * d.stride[a];
+        const int64_t e1 = (int64_t)(dims[a] - 1 + s.reach) * d.stride[a];
+        mn += std::min(e0, e1);
+        mx += std::max(e0, e1);
+        const int64_t ext = (int64_t)(dims[a] + 2 * s.reach) * std::llabs(d.stride[a]);
+        if (ext >= ((int64_t)1 << 31))
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': axis %d spans 2 GiB or more", s.name.c_str(), a);
+        s.stride[a] = (int32_t)d.stride[a];
+    }
+    const char* c0 = static_cast<const char*>(d.comp[0]);
+    s.packed = 1;
+    for (int c = 1; c < d.f_dim; ++c)
+        if (static_cast<const char*>(d.comp[c]) - c0 != (int64_t)c * es) s.packed = 0;
+    const int64_t span = mx - mn + (s.packed ? (int64_t)d.f_dim * es : es);
+    if (span <= 0 || span >= ((int64_t)1 << 31))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': readable extent %lld bytes must be below 2 GiB",
+                       s.name.c_str(), (long long)span);
+    for (int c = 0; c < 4; ++c) {
+        s.base[c] = 0;
+        s.num_records[c] = 0;
+        s.comp_off[c] = 0;
+    }
+    if (s.packed) {
+        s.base[0] = (uint64_t)(reinterpret_cast<uintptr_t>(c0) + mn);
+        s.num_records[0] = (uint32_t)span;
+        for (int c = 0; c < d.f_dim; ++c) s.comp_off[c] = (int32_t)(-mn + (int64_t)c * es);
+    } else {
+        for (int c = 0; c < d.f_dim; ++c) {
+            s.base[c] = (uint64_t)(reinterpret_cast<uintptr_t>(d.comp[c]) + mn);
+            s.num_records[c] = (uint32_t)span;
+            s.comp_off[c] = (int32_t)(-mn);
+        }
+    }
+    return ISAAC_OK;
+}
+
+bool finite3(const double v[3]) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+struct CameraBasis {
+    double fwd[3], right[3], upp[3], h, aspect;
+};
+
+bool camera_basis(const isaac_render_desc& j, CameraBasis& cb, std::string& err) {
+    double f[3] = {j.center[0] - j.eye[0], j.center[1] - j.eye[1], j.center[2] - j.eye[2]};
+    double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(fl > 0.0) || !std::isfinite(fl)) {
+        err = "eye and center must differ";
+        return false;
+    }
+    for (int a = 0; a < 3; ++a) cb.fwd[a] = f[a] / fl;
+    const double* u = j.up;
+    double r[3] = {cb.fwd[1] * u[2] - cb.fwd[2] * u[1], cb.fwd[2] * u[0] - cb.fwd[0] * u[2],
+                   cb.fwd[0] * u[1] - cb.fwd[1] * u[0]};
+    double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rl > 0.0) || !std::isfinite(rl)) {
+        err = "up must not be parallel to the view direction";
+        return false;
+    }
+    for (int a = 0; a < 3; ++a) cb.right[a] = r[a] / rl;
+    cb.upp[0] = cb.right[1] * cb.fwd[2] - cb.right[2] * cb.fwd[1];
+    cb.upp[1] = cb.right[2] * cb.fwd[0] - cb.right[0] * cb.fwd[2];
+    cb.upp[2] = cb.right[0] * cb.fwd[1] - cb.right[1] * cb.fwd[0];
+    if (j.projection == ISAAC_ORTHOGRAPHIC) {
+        cb.h = 0.5 * j.ortho_height;
+    } else {
+        cb.h = std::tan(0.5 * j.fovy_deg * kPi / 180.0);
+    }
+    cb.aspect = (double)j.width / (double)j.height;
+    return true;
+}
+
+int size_class_of(int w, int h) {
+    int m = std::max(w, h), c = 0;
+    while ((1 << c) < m && c < 15) ++c;
+    return c;
+}
+
+// Validate one job and build its device block (without writing anything shared).
+isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need_out, DevJob& dj,
+                       int* n_active_out) {
+    if (j.volume_id < 0 || j.volume_id >= (int)ctx->volumes.size() || !ctx->volumes[j.volume_id].defined)
+        return set_err(ctx, ISAAC_ERR_NOT_FOUND, "volume %d is not defined", j.volume_id);
+    const Volume& v = ctx->volumes[j.volume_id];
+    if (j.width < 1 || j.height < 1 || j.width > 32768 || j.height > 32768)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "image size %dx%d outside 1..32768", j.width, j.height);
+    if (j.projection != ISAAC_PERSPECTIVE && j.projection != ISAAC_ORTHOGRAPHIC)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "unknown projection %d", j.projection);
+    if (!finite3(j.eye) || !finite3(j.center) || !finite3(j.up))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "camera vectors must be finite");
+    if (j.projection == ISAAC_PERSPECTIVE && !(j.fovy_deg > 0.0 && j.fovy_deg < 180.0))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "fovy_deg must lie in (0,180)");
+    if (j.projection == ISAAC_ORTHOGRAPHIC && !(j.ortho_height > 0.0 && std::isfinite(j.ortho_height)))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "ortho_height must be positive");
+    if (!(j.step > 0.0 && std::isfinite(j.step)))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "step must be positive");
+    {
+        const double diag = std::sqrt((double)v.dims[0] * v.dims[0] + (double)v.dims[1] * v.dims[1] +
+                                      (double)v.dims[2] * v.dims[2]);
+        if (diag / j.step > 1e9)
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "step too small: more than 1e9 samples per ray");
+    }
+    if (j.interpolation != ISAAC_NEAREST && j.interpolation != ISAAC_TRILINEAR)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "unknown interpolation %d", j.interpolation);
+    if (j.n_clip < 0 || j.n_clip > kMaxClip || (j.n_clip > 0 && !j.clip))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "n_clip must be 0..%d with a plane array", kMaxClip);
+    if (!(j.ert_threshold >= 0.0f) || !std::isfinite(j.ert_threshold))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "ert_threshold must be >= 0");
+    if (need_out && !j.out_rgba) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "out_rgba is NULL");
+    CameraBasis cb;
+    std::string err;
+    if (!camera_basis(j, cb, err)) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "%s", err.c_str());
+    std::memset(&dj, 0, sizeof dj);
+    for (int a = 0; a < 3; ++a) {
+        dj.eye[a] = j.eye[a];
+        dj.fwd[a] = cb.fwd[a];
+        dj.right[a] = cb.right[a];
+        dj.upp[a] = cb.upp[a];
+        dj.dims[a] = v.dims[a];
+    }
+    dj.h = cb.h;
+    dj.aspect = cb.aspect;
+    dj.step = j.step;
+    dj.ortho = j.projection == ISAAC_ORTHOGRAPHIC;
+    dj.width = j.width;
+    dj.height = j.height;
+    dj.interp = j.interpolation;
+    dj.n_clip = j.n_clip;
+    for (int c = 0; c < j.n_clip; ++c) {
+        const isaac_clip_plane& p = j.clip[c];
+        const double nn = p.n[0] * p.n[0] + p.n[1] * p.n[1] + p.n[2] * p.n[2];
+        if (!(nn > 0.0) || !std::isfinite(nn) || !std::isfinite(p.d))
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "clip plane %d needs a finite non-zero normal", c);
+        dj.clip[c][0] = p.n[0];
+        dj.clip[c][1] = p.n[1];
+        dj.clip[c][2] = p.n[2];
+        dj.clip[c][3] = p.d;
+    }
+    dj.ert = j.ert_threshold == 0.0f ? 0.999f : j.ert_threshold;
+    const TileShape& ts = ctx->shapes[size_class_of(j.width, j.height)];
+    dj.wave_w = ts.wave_w;
+    dj.waves_x = ts.waves_x;
+    dj.unroll = ts.unroll;
+    const int tw = ts.wave_w * ts.waves_x, th = (64 / ts.wave_w) * (4 / ts.waves_x);
+    dj.tiles_x = (j.width + tw - 1) / tw;
+    dj.tiles_y = (j.height + th - 1) / th;
+    dj.out = j.out_rgba;
+    dj.out_samples = j.out_samples;
+    int n_act = 0;
+    for (int s = 0; s < (int)v.src.size(); ++s) {
+        const SourceHost& sh = v.src[s];
+        const bool en = j.enabled ? j.enabled[s] != 0 : sh.desc.enabled != 0;
+        const float w = j.weights ? j.weights[s] : sh.desc.weight;
+        if (!(w >= 0.0f && w <= 1.0f))
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "weight of source %d must lie in [0,1]", s);
+        int32_t tf = j.tf_handles ? j.tf_handles[s] : v.tf[s];
+        if (tf < 0 || tf >= ctx->tf_capacity || !ctx->tf_slots[tf].live || (j.tf_handles && tf == 0))
+            return set_err(ctx, ISAAC_ERR_NOT_FOUND, "transfer table handle %d of source %d is not live", tf, s);
+        if (!en || w == 0.0f) continue;   // never read: a zero weight contributes exactly nothing
+        if (!sh.desc.comp[0] && !sh.shadow)
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source %d is enabled but has no data", s);
+        DevSource& ds = dj.src[n_act++];
+        ds.packed = sh.packed;
+        for (int c = 0; c < 4; ++c) {
+            ds.base[c] = sh.base[c];
+            ds.num_records[c] = sh.num_records[c];
+            ds.comp_off[c] = sh.comp_off[c];
+        }
+        for (int a = 0; a < 3; ++a) ds.stride[a] = sh.stride[a];
+        ds.f_dim = sh.desc.f_dim;
+        ds.dtype = sh.desc.dtype;
+        ds.guard = sh.reach;
+        ds.n_ops = sh.chain.n_ops;
+        for (int o = 0; o < sh.chain.n_ops; ++o) ds.ops[o] = sh.chain.ops[o];
+        ds.tf_slot = tf;
+        ds.weight = w;
+    }
+    dj.n_src = n_act;
+    *n_active_out = n_act;
+    return ISAAC_OK;
+}
+
+// update() callbacks and copies of non-persistent sources for the volumes of a call
+isaac_status prepare_sources(isaac_context* ctx, const isaac_render_desc* jobs, int n) {
+    std::vector<int> vols;
+    for (int i = 0; i < n; ++i)
+        if (std::find(vols.begin(), vols.end(), jobs[i].volume_id) == vols.end()) vols.push_back(jobs[i].volume_id);
+    for (int vid : vols) {
+        Volume& v = ctx->volumes[vid];
+        for (int s = 0; s < (int)v.src.size(); ++s) {
+            SourceHost& sh = v.src[s];
+            bool en = false;
+            for (int i = 0; i < n; ++i)
+                if (jobs[i].volume_id == vid) en = en || (jobs[i].enabled ? jobs[i].enabled[s] != 0 : sh.desc.enabled != 0);
+            void* ptr = nullptr;
+            for (int i = 0; i < n; ++i)
+                if (jobs[i].volume_id == vid) {
+                    ptr = jobs[i].update_pointer;
+                    break;
+                }
+            if (sh.desc.update) sh.desc.update(sh.desc.user, en ? 1 : 0, ptr);
+            if (!sh.desc.persistent && en) {
+                const int es = esize_of(sh.desc.dtype);
+                const int64_t ex = v.dims[0] + 2 * sh.reach, ey = v.dims[1] + 2 * sh.reach;
+                int64_t dst_stride[3] = {(int64_t)sh.desc.f_dim * es, (int64_t)sh.desc.f_dim * es * ex,
+                                         (int64_t)sh.desc.f_dim * es * ex * ey};
+                char* dst0 = static_cast<char*>(sh.shadow) +
+                             sh.reach * (dst_stride[0] + dst_stride[1] + dst_stride[2]);
+                int32_t lo[3] = {-sh.reach, -sh.reach, -sh.reach};
+                int32_t ext[3] = {v.dims[0] + 2 * sh.reach, v.dims[1] + 2 * sh.reach, v.dims[2] + 2 * sh.reach};
+                int rc = launch_strided_copy(sh.desc.comp, sh.desc.stride, dst0, dst_stride, es, sh.desc.f_dim, lo, ext,
+                                             ctx->stream);
+                if (rc != hipSuccess)
+                    return set_err(ctx, ISAAC_ERR_DEVICE, "strided copy: %s", hipGetErrorString((hipError_t)rc));
+                // the next update() may reuse the buffer this copy reads
+                HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            }
+        }
+    }
+    return ISAAC_OK;
+}
+
+isaac_status acquire_slot(isaac_context* ctx, RingSlot** out) {
+    RingSlot& r = ctx->ring[ctx->ring_next];
+    ctx->ring_next = (ctx->ring_next + 1) % kRingSlots;
+    if (r.busy) {
+        HIP_TRY(ctx, hipEventSynchronize(r.done));
+        r.busy = false;
+    }
+    *out = &r;
+    return ISAAC_OK;
+}
+
+isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, const std::vector<DevJob>& djs,
+                          int max_src, unsigned flags, hipStream_t stream) {
+    const int n = (int)djs.size();
+    RingSlot* r = nullptr;
+    isaac_status st = acquire_slot(ctx, &r);
+    if (st) return st;
+    int tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        r->host[i] = djs[i];
+        r->host[i].tile_begin = tiles;
+        tiles += djs[i].tiles_x * djs[i].tiles_y;
+    }
+    const uint64_t seq = ++ctx->seq;
+    // mark every table read by this call
+    for (const DevJob& dj : djs)
+        for (int s = 0; s < dj.n_src; ++s) ctx->tf_slots[dj.src[s].tf_slot].last_use = seq;
+    (void)jobs;
+    LaunchArgs la;
+    la.jobs = r->dev;
+    la.n_jobs = n;
+    la.total_tiles = tiles;
+    la.tf_pool = ctx->tf_pool;
+    la.cursor = r->cursor;
+    la.persistent = n > 1 ? 1 : 0;
+    la.grid = std::max(1, ctx->n_cu * ctx->blocks_per_cu);
+    la.max_src = std::max(1, max_src);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (flags & ISAAC_TIMING) {
+        t0 = get_event(ctx);
+        t1 = get_event(ctx);
+        if (!t0 || !t1) return set_err(ctx, ISAAC_ERR_DEVICE, "hipEventCreate failed");
+    }
+    const bool use_graph = n > 1 && !(flags & ISAAC_NO_GRAPH);
+    if (use_graph) {
+        if (!r->exec || r->g_jobs != n || r->g_tiles != tiles || r->g_grid != la.grid || r->g_src != la.max_src) {
+            if (r->exec) hipGraphExecDestroy(r->exec);
+            if (r->graph) hipGraphDestroy(r->graph);
+            r->exec = nullptr;
+            r->graph = nullptr;
+            HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipMemcpyAsync(r->dev, r->host, sizeof(DevJob) * n, hipMemcpyHostToDevice, ctx->cap_stream);
+            if (e == hipSuccess) e = (hipError_t)launch_reset_counter(r->cursor, ctx->cap_stream);
+            if (e == hipSuccess) e = (hipError_t)launch_raycast(la, ctx->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                return set_err(ctx, ISAAC_ERR_DEVICE, "graph capture failed: %s",
+                               hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            r->graph = g;
+            HIP_TRY(ctx, hipGraphInstantiate(&r->exec, g, nullptr, nullptr, 0));
+            r->g_jobs = n;
+            r->g_tiles = tiles;
+            r->g_grid = la.grid;
+            r->g_src = la.max_src;
+        }
+        if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
+        HIP_TRY(ctx, hipGraphLaunch(r->exec, stream));
+        if (t1) HIP_TRY(ctx, hipEventRecord(t1, stream));
+    } else {
+        HIP_TRY(ctx, hipMemcpyAsync(r->dev, r->host, sizeof(DevJob) * n, hipMemcpyHostToDevice, stream));
+        if (la.persistent) {
+            int rc = launch_reset_counter(r->cursor, stream);
+            if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "counter reset: %s", hipGetErrorString((hipError_t)rc));
+        }
+        if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
+        int rc = launch_raycast(la, stream);
+        if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "raycast launch: %s", hipGetErrorString((hipError_t)rc));
+        if (t1) HIP_TRY(ctx, hipEventRecord(t1, stream));
+    }
+    if (t0) ctx->timed.emplace_back(t0, t1);
+    HIP_TRY(ctx, hipEventRecord(r->done, stream));
+    r->busy = true;
+    hipEvent_t pe = get_event(ctx);
+    if (!pe) return set_err(ctx, ISAAC_ERR_DEVICE, "hipEventCreate failed");
+    HIP_TRY(ctx, hipEventRecord(pe, stream));
+    ctx->pending.push_back({seq, pe});
+    return ISAAC_OK;
+}
+
+isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int n, unsigned flags, bool need_out,
+                         hipStream_t stream) {
+    if (n < 1 || n > kMaxBatch || !jobs)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "n_jobs must be 1..%d", kMaxBatch);
+    std::vector<DevJob> djs(n);
+    int max_src = 1;
+    for (int i = 0; i < n; ++i) {
+        int na = 0;
+        isaac_status st = build_job(ctx, jobs[i], need_out, djs[i], &na);
+        if (st) return st;
+        max_src = std::max(max_src, na);
+    }
+    isaac_status st = prepare_sources(ctx, jobs, n);
+    if (st) return st;
+    // non-persistent sources read their shadow copies
+    for (int i = 0; i < n; ++i) {
+        const Volume& v = ctx->volumes[jobs[i].volume_id];
+        int k = 0;
+        for (int s = 0; s < (int)v.src.size(); ++s) {
+            const SourceHost& sh = v.src[s];
+            const bool en = jobs[i].enabled ? jobs[i].enabled[s] != 0 : sh.desc.enabled != 0;
+            const float w = jobs[i].weights ? jobs[i].weights[s] : sh.desc.weight;
+            if (!en || w == 0.0f) continue;
+            if (!sh.desc.persistent) {
+                DevSource& ds = djs[i].src[k];
+                const int es = esize_of(sh.desc.dtype);
+                const int64_t ex = v.dims[0] + 2 * sh.reach, ey = v.dims[1] + 2 * sh.reach;
+                ds.base[0] = reinterpret_cast<uint64_t>(sh.shadow);
+                ds.num_records[0] = (uint32_t)sh.shadow_bytes;
+                ds.stride[0] = sh.desc.f_dim * es;
+                ds.stride[1] = (int32_t)(sh.desc.f_dim * es * ex);
+                ds.stride[2] = (int32_t)(sh.desc.f_dim * es * ex * ey);
+                const int32_t o = sh.reach * (ds.stride[0] + ds.stride[1] + ds.stride[2]);
+                for (int c = 0; c < 4; ++c) ds.comp_off[c] = o + c * es;
+                ds.packed = 1;
+            }
+            ++k;
+        }
+    }
+    st = enqueue_jobs(ctx, jobs, djs, max_src, flags, stream);
+    if (st) return st;
+    if (!(flags & ISAAC_ASYNC)) {
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        update_completed(ctx);
+    }
+    return ISAAC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* isaac_version(void) { return "isaac-mi355x 0.1 (gfx950)"; }
+
+const char* isaac_init_error(void) { return g_init_error.c_str(); }
+
+const char* isaac_last_error(const isaac_context* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+isaac_status isaac_check_functor_chain(const char* chain, int f_dim, int* out_dim, int* out_ops, char* err,
+                                       int errlen) {
+    CompiledChain c;
+    std::string e;
+    if (!compile_chain(chain, f_dim, c, e)) {
+        if (err && errlen > 0) std::snprintf(err, (size_t)errlen, "%s", e.c_str());
+        return ISAAC_ERR_BAD_FUNCTOR;
+    }
+    if (out_dim) *out_dim = c.out_dim;
+    if (out_ops) *out_ops = c.n_ops;
+    if (err && errlen > 0) err[0] = 0;
+    return ISAAC_OK;
+}
+
+isaac_status isaac_init(const isaac_init_desc* desc, isaac_context** out) {
+    if (!out) return ISAAC_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    isaac_init_desc d{};
+    if (desc) d = *desc;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev < 1) {
+        g_init_error = "no HIP device";
+        return ISAAC_ERR_DEVICE;
+    }
+    if (d.device < 0 || d.device >= n_dev) {
+        g_init_error = "device ordinal out of range";
+        return ISAAC_ERR_INVALID_ARGUMENT;
+    }
+    auto* ctx = new isaac_context();
+    ctx->device = d.device;
+    ctx->budget = d.mem_budget_bytes ? d.mem_budget_bytes : ((size_t)1 << 30);
+    ctx->max_inflight = d.max_inflight > 0 ? d.max_inflight : 64;
+    ctx->volumes.resize(d.max_volumes > 0 ? d.max_volumes : 256);
+    auto fail = [&](const char* what, hipError_t e) {
+        g_init_error = std::string(what) + ": " + hipGetErrorString(e);
+        isaac_destroy(ctx);
+        return ISAAC_ERR_DEVICE;
+    };
+    hipError_t e = hipSetDevice(d.device);
+    if (e != hipSuccess) return fail("hipSetDevice", e);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, d.device);
+    if (e != hipSuccess) return fail("hipGetDeviceProperties", e);
+    ctx->n_cu = prop.multiProcessorCount;
+    int bpc = 1;
+    if (raycast_occupancy(&bpc) == hipSuccess && bpc > 0) ctx->blocks_per_cu = bpc;
+    if (d.stream) {
+        ctx->stream = static_cast<hipStream_t>(d.stream);
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail("hipStreamCreate", e);
+        ctx->own_stream = true;
+    }
+    e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail("hipStreamCreate", e);
+    for (int i = 0; i < 4; ++i) {
+        hipStream_t s = nullptr;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail("hipStreamCreate", e);
+        ctx->serve_streams.push_back(s);
+    }
+    for (int i = 0; i < kRingSlots; ++i) {
+        RingSlot& r = ctx->ring[i];
+        e = hipHostMalloc((void**)&r.host, sizeof(DevJob) * kMaxBatch);
+        if (e == hipSuccess) e = hipMalloc((void**)&r.dev, sizeof(DevJob) * kMaxBatch);
+        if (e == hipSuccess) e = hipMalloc((void**)&r.cursor, 64);
+        if (e == hipSuccess) e = hipMemset(r.cursor, 0, 64);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
+        if (e != hipSuccess) return fail("staging ring", e);
+    }
+    e = hipMalloc((void**)&ctx->tf_pool, (size_t)kTfSlots * kTfEntries * 4 * sizeof(float));
+    if (e != hipSuccess) return fail("transfer table pool", e);
+    ctx->tf_capacity = kTfSlots;
+    ctx->tf_slots.resize(kTfSlots);
+    // slot 0: the all-zero table of sources without a transfer function
+    e = hipMemset(ctx->tf_pool, 0, kTfEntries * 4 * sizeof(float));
+    if (e != hipSuccess) return fail("hipMemset", e);
+    ctx->tf_slots[0].live = true;
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail("hipDeviceSynchronize", e);
+    *out = ctx;
+    return ISAAC_OK;
+}
+
+void isaac_destroy(isaac_context* ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    for (hipStream_t s : ctx->serve_streams) hipStreamSynchronize(s);
+    hipDeviceSynchronize();
+    for (auto& v : ctx->volumes)
+        for (auto& s : v.src)
+            if (s.shadow) hipFree(s.shadow);
+    for (auto& kv : ctx->tickets) {
+        if (kv.second.out) hipFree(kv.second.out);
+        if (kv.second.ev) hipEventDestroy(kv.second.ev);
+    }
+    for (auto& kv : ctx->image_cache) hipFree(kv.second);
+    for (auto& r : ctx->ring) {
+        if (r.exec) hipGraphExecDestroy(r.exec);
+        if (r.graph) hipGraphDestroy(r.graph);
+        if (r.host) hipHostFree(r.host);
+        if (r.dev) hipFree(r.dev);
+        if (r.cursor) hipFree(r.cursor);
+        if (r.done) hipEventDestroy(r.done);
+    }
+    for (auto& p : ctx->pending) hipEventDestroy(p.ev);
+    for (auto& t : ctx->timed) {
+        hipEventDestroy(t.first);
+        hipEventDestroy(t.second);
+    }
+    for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
+    if (ctx->tf_pool) hipFree(ctx->tf_pool);
+    for (hipStream_t s : ctx->serve_streams) hipStreamDestroy(s);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+isaac_status isaac_set_sources(isaac_context* ctx, int volume_id, const int32_t dims[3], const isaac_source_desc* src,
+                               int n_src) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (volume_id < 0 || volume_id >= (int)ctx->volumes.size())
+        return set_err(ctx, ISAAC_ERR_NOT_FOUND, "volume id %d outside 0..%d", volume_id, (int)ctx->volumes.size() - 1);
+    if (!dims) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "dims is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > (1 << 20))
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "dims[%d] = %d outside 1..2^20", a, dims[a]);
+    if (n_src < 0 || n_src > kMaxSources || (n_src > 0 && !src))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "n_src must be 0..%d", kMaxSources);
+    std::vector<SourceHost> hs(n_src);
+    for (int s = 0; s < n_src; ++s) {
+        SourceHost& h = hs[s];
+        h.desc = src[s];
+        h.name = src[s].name ? src[s].name : ("source" + std::to_string(s));
+        h.chain_text = src[s].functor_chain ? src[s].functor_chain : "";
+        h.desc.name = nullptr;
+        h.desc.functor_chain = nullptr;
+        const isaac_source_desc& d = src[s];
+        if (d.f_dim < 1 || d.f_dim > 4)
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': f_dim %d outside 1..4", h.name.c_str(), d.f_dim);
+        if (d.dtype != ISAAC_F32 && d.dtype != ISAAC_F16 && d.dtype != ISAAC_BF16)
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': unknown dtype", h.name.c_str());
+        if (d.guard < 0) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': guard < 0", h.name.c_str());
+        if (!(d.weight >= 0.0f && d.weight <= 1.0f))
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': weight must lie in [0,1]", h.name.c_str());
+        std::string err;
+        if (!compile_chain(h.chain_text.c_str(), d.f_dim, h.chain, err))
+            return set_err(ctx, ISAAC_ERR_BAD_FUNCTOR, "source '%s': %s", h.name.c_str(), err.c_str());
+        const int es = esize_of(d.dtype);
+        bool have = true;
+        for (int c = 0; c < d.f_dim; ++c) have = have && d.comp[c] != nullptr;
+        if (!have) {
+            if (d.enabled)
+                return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': enabled with a NULL component",
+                               h.name.c_str());
+            h.desc.comp[0] = nullptr;   // never read
+            continue;
+        }
+        for (int c = 0; c < d.f_dim; ++c)
+            if (reinterpret_cast<uintptr_t>(d.comp[c]) % es)
+                return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': component %d misaligned", h.name.c_str(), c);
+        for (int a = 0; a < 3; ++a)
+            if (d.stride[a] % es)
+                return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source '%s': stride %d not a multiple of %d bytes",
+                               h.name.c_str(), a, es);
+        st = derive_layout(ctx, dims, h);
+        if (st) return st;
+    }
+    // allocate shadows for non-persistent sources (all or nothing)
+    for (int s = 0; s < n_src; ++s) {
+        SourceHost& h = hs[s];
+        if (h.desc.persistent || !h.desc.comp[0]) continue;
+        const int reach = h.desc.guard >= 1 ? 1 : 0;
+        h.shadow_bytes = (size_t)esize_of(h.desc.dtype) * h.desc.f_dim * (dims[0] + 2 * reach) *
+                         (size_t)(dims[1] + 2 * reach) * (dims[2] + 2 * reach);
+        if (h.shadow_bytes >= ((size_t)1 << 31)) {
+            for (auto& x : hs)
+                if (x.shadow) hipFree(x.shadow);
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "non-persistent source '%s' larger than 2 GiB",
+                           h.name.c_str());
+        }
+        if (hipMalloc(&h.shadow, h.shadow_bytes) != hipSuccess) {
+            for (auto& x : hs)
+                if (x.shadow) hipFree(x.shadow);
+            return set_err(ctx, ISAAC_ERR_OUT_OF_MEMORY, "no memory for the copy of source '%s'", h.name.c_str());
+        }
+    }
+    Volume& v = ctx->volumes[volume_id];
+    if (v.defined) {
+        hipStreamSynchronize(ctx->stream);
+        for (auto& s : v.src)
+            if (s.shadow) hipFree(s.shadow);
+    }
+    std::vector<int32_t> tf(n_src, 0);
+    for (int s = 0; s < n_src && s < (int)v.tf.size(); ++s) tf[s] = v.tf[s];
+    v.defined = true;
+    for (int a = 0; a < 3; ++a) v.dims[a] = dims[a];
+    v.src = std::move(hs);
+    v.tf = tf;
+    return ISAAC_OK;
+}
+
+isaac_status isaac_set_transfer(isaac_context* ctx, int volume_id, int source, const isaac_tf_point* pts, int n_pts,
+                                int32_t* out_handle) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (volume_id < 0 || volume_id >= (int)ctx->volumes.size() || !ctx->volumes[volume_id].defined)
+        return set_err(ctx, ISAAC_ERR_NOT_FOUND, "volume %d is not defined", volume_id);
+    Volume& v = ctx->volumes[volume_id];
+    if (source < 0 || source >= (int)v.src.size())
+        return set_err(ctx, ISAAC_ERR_NOT_FOUND, "volume %d has no source %d", volume_id, source);
+    float table[kTfEntries * 4];
+    std::string err;
+    if (!bake_tf(pts, n_pts, table, err)) return set_err(ctx, ISAAC_ERR_BAD_TRANSFER, "%s", err.c_str());
+    int32_t h = -1;
+    st = new_tf_slot(ctx, table, &h);
+    if (st) return st;
+    v.tf[source] = h;
+    if (out_handle) *out_handle = h;
+    return ISAAC_OK;
+}
+
+isaac_status isaac_release_transfer(isaac_context* ctx, int32_t handle) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (handle <= 0 || handle >= ctx->tf_capacity || !ctx->tf_slots[handle].live || ctx->tf_slots[handle].released)
+        return set_err(ctx, ISAAC_ERR_NOT_FOUND, "transfer handle %d is not live", handle);
+    ctx->tf_slots[handle].released = true;   // a current table stays until replaced
+    update_completed(ctx);
+    return ISAAC_OK;
+}
+
+isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    return render_impl(ctx, jobs, n_jobs, flags, true, ctx->stream);
+}
+
+isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    double sum = 0.0;
+    int n = 0;
+    for (auto& t : ctx->timed) {
+        HIP_TRY(ctx, hipEventSynchronize(t.second));
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, t.first, t.second));
+        sum += ms;
+        ++n;
+        put_event(ctx, t.first);
+        put_event(ctx, t.second);
+    }
+    ctx->timed.clear();
+    if (total_ms) *total_ms = sum;
+    if (count) *count = n;
+    return ISAAC_OK;
+}
+
+isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w, int waves_x, int unroll) {
+    if (!ctx) return ISAAC_ERR_INVALID_ARGUMENT;
+    if (size_class < 0 || size_class > 15 || (wave_w != 8 && wave_w != 16 && wave_w != 32 && wave_w != 64) ||
+        (waves_x != 1 && waves_x != 2 && waves_x != 4) || (unroll != 1 && unroll != 2 && unroll != 4))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "invalid tile shape");
+    ctx->shapes[size_class] = TileShape{wave_w, waves_x, unroll};
+    return ISAAC_OK;
+}
+
+isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_w, int* waves_x, int* unroll) {
+    if (!ctx || size_class < 0 || size_class > 15) return ISAAC_ERR_INVALID_ARGUMENT;
+    if (wave_w) *wave_w = ctx->shapes[size_class].wave_w;
+    if (waves_x) *waves_x = ctx->shapes[size_class].waves_x;
+    if (unroll) *unroll = ctx->shapes[size_class].unroll;
+    return ISAAC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving
+// ---------------------------------------------------------------------------
+isaac_status isaac_submit_batch(isaac_context* ctx, const isaac_render_desc* jobs, int n, uint64_t* tickets) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (n < 1 || n > kMaxBatch || !jobs || !tickets)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "n_jobs must be 1..%d with a ticket array", kMaxBatch);
+    size_t need = 0;
+    for (int i = 0; i < n; ++i) {
+        if (jobs[i].width < 1 || jobs[i].height < 1 || jobs[i].width > 32768 || jobs[i].height > 32768)
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "image size out of range");
+        need += (size_t)jobs[i].width * jobs[i].height * 4 * sizeof(float);
+    }
+    size_t inflight = ctx->tickets.size();
+    if ((int)(inflight + n) > ctx->max_inflight || ctx->used + need > ctx->budget)
+        return set_err(ctx, ISAAC_ERR_BUSY, "admission refused: %zu + %zu bytes of %zu, %zu in flight", ctx->used, need,
+                       ctx->budget, inflight);
+    // validate before allocating anything
+    std::vector<isaac_render_desc> js(jobs, jobs + n);
+    for (int i = 0; i < n; ++i) {
+        DevJob tmp;
+        int na = 0;
+        js[i].out_rgba = reinterpret_cast<float*>(16);   // placeholder for validation only
+        js[i].out_samples = nullptr;
+        st = build_job(ctx, js[i], true, tmp, &na);
+        if (st) return st;
+    }
+    std::vector<Ticket> made;
+    for (int i = 0; i < n; ++i) {
+        Ticket t;
+        t.id = ctx->next_ticket++;
+        t.bytes = (size_t)jobs[i].width * jobs[i].height * 4 * sizeof(float);
+        auto it = ctx->image_cache.find(t.bytes);
+        if (it != ctx->image_cache.end()) {
+            t.out = it->second;
+            ctx->image_cache.erase(it);
+            ctx->cached -= t.bytes;
+        } else if (hipMalloc((void**)&t.out, t.bytes) != hipSuccess) {
+            for (auto& m : made) {
+                ctx->image_cache.emplace(m.bytes, m.out);
+                ctx->cached += m.bytes;
+            }
+            return set_err(ctx, ISAAC_ERR_OUT_OF_MEMORY, "image allocation failed");
+        }
+        js[i].out_rgba = t.out;
+        made.push_back(t);
+    }
+    hipStream_t s = ctx->serve_streams[ctx->serve_rr];
+    ctx->serve_rr = (ctx->serve_rr + 1) % (int)ctx->serve_streams.size();
+    st = render_impl(ctx, js.data(), n, ISAAC_ASYNC | ISAAC_NO_GRAPH, true, s);
+    if (st) {
+        for (auto& m : made) {
+            ctx->image_cache.emplace(m.bytes, m.out);
+            ctx->cached += m.bytes;
+        }
+        return st;
+    }
+    hipEvent_t ev = nullptr;
+    for (int i = 0; i < n; ++i) {
+        Ticket& t = made[i];
+        t.ev = get_event(ctx);
+        if (!t.ev) return set_err(ctx, ISAAC_ERR_DEVICE, "hipEventCreate failed");
+        HIP_TRY(ctx, hipEventRecord(t.ev, s));
+        ctx->used += t.bytes;
+        tickets[i] = t.id;
+        ctx->tickets[t.id] = t;
+    }
+    (void)ev;
+    // keep the cache of freed images within what the budget leaves
+    while (ctx->cached > 0 && ctx->cached + ctx->used > ctx->budget) {
+        auto it = ctx->image_cache.begin();
+        ctx->cached -= it->first;
+        hipFree(it->second);
+        ctx->image_cache.erase(it);
+    }
+    return ISAAC_OK;
+}
+
+isaac_status isaac_submit(isaac_context* ctx, const isaac_render_desc* job, uint64_t* out_ticket) {
+    return isaac_submit_batch(ctx, job, 1, out_ticket);
+}
+
+isaac_status isaac_poll(isaac_context* ctx, uint64_t ticket, int* done, const float** out_rgba) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) return set_err(ctx, ISAAC_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Ticket& t = it->second;
+    if (!t.done) {
+        hipError_t e = hipEventQuery(t.ev);
+        if (e == hipSuccess) t.done = true;
+        else if (e != hipErrorNotReady) return set_err(ctx, ISAAC_ERR_DEVICE, "request failed: %s", hipGetErrorString(e));
+    }
+    if (done) *done = t.done ? 1 : 0;
+    if (out_rgba) *out_rgba = t.done ? t.out : nullptr;
+    return ISAAC_OK;
+}
+
+isaac_status isaac_release(isaac_context* ctx, uint64_t ticket) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) return set_err(ctx, ISAAC_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Ticket& t = it->second;
+    if (!t.done) HIP_TRY(ctx, hipEventSynchronize(t.ev));
+    put_event(ctx, t.ev);
+    ctx->used -= t.bytes;
+    ctx->image_cache.emplace(t.bytes, t.out);
+    ctx->cached += t.bytes;
+    ctx->tickets.erase(it);
+    update_completed(ctx);
+    return ISAAC_OK;
+}
+
+isaac_status isaac_serving_usage(isaac_context* ctx, size_t* used, size_t* budget, int* inflight) {
+    if (!ctx) return ISAAC_ERR_INVALID_ARGUMENT;
+    if (used) *used = ctx->used;
+    if (budget) *budget = ctx->budget;
+    if (inflight) *inflight = (int)ctx->tickets.size();
+    return ISAAC_OK;
+}
+
+}  // extern "C"

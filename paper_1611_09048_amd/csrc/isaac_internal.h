@@ -1,0 +1,102 @@
+// Library-private structures shared by the host runtime (isaac_api.cpp) and
+// the HIP kernels (raycast.hip).  Plain data only; everything a kernel needs
+// for one job is in DevJob, built on the host and copied to device memory.
+#pragma once
+
+#include <stdint.h>
+
+namespace isaac {
+
+constexpr int kMaxSources = 8;
+constexpr int kMaxOps = 8;
+constexpr int kMaxClip = 8;
+constexpr int kTfEntries = 256;
+constexpr int kMaxBatch = 256;
+constexpr int kBlockThreads = 256;     // 4 waves of 64
+
+// Functor bytecode.  ADD/MUL/POW act componentwise on the first `dim`
+// components, LENGTH and SUM reduce to one component; SQRT and SQUARE are
+// the host's rewrites of pow(0.5) and pow(2) with all arguments equal.
+enum OpKind : int32_t {
+    OP_ADD = 0,
+    OP_MUL = 1,
+    OP_POW = 2,
+    OP_LENGTH = 3,
+    OP_SUM = 4,
+    OP_SQRT = 5,
+    OP_SQUARE = 6,
+};
+
+struct DevOp {
+    int32_t kind;
+    int32_t dim;          // components the op reads
+    float arg[4];
+};
+
+enum DType : int32_t { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+
+struct DevSource {
+    uint64_t base[4];      // per component: lowest byte address it can be read at
+    uint32_t num_records[4];  // per component: bytes readable from base (buffer-resource range)
+    int32_t comp_off[4];   // byte offset of component c of voxel (0,0,0) from base[c]
+    int32_t packed;        // components adjacent in memory: one range (index 0), one wide load
+    int32_t stride[3];     // byte strides along x, y, z
+    int32_t f_dim;
+    int32_t dtype;
+    int32_t guard;         // >= 1: corners may reach index -1 and N; 0: clamp to the border
+    int32_t n_ops;
+    int32_t tf_slot;       // index into the transfer-table pool
+    float weight;
+    int32_t pad;
+    DevOp ops[kMaxOps];
+};
+
+struct DevJob {
+    // camera, FP64 (host-computed basis; per-ray setup stays FP64 on the device)
+    double eye[3];
+    double fwd[3];
+    double right[3];
+    double upp[3];
+    double h;              // tan(fovy/2), or ortho_height/2
+    double aspect;         // width / height
+    double step;
+    double clip[kMaxClip][4];
+    int32_t ortho;
+    int32_t width, height;
+    int32_t interp;
+    int32_t dims[3];
+    int32_t n_src;         // active sources, compacted in index order
+    int32_t n_clip;
+    float ert;             // early-termination threshold
+    // tile decomposition of this job's image
+    int32_t wave_w;        // rays per wave: wave_w x (64 / wave_w)
+    int32_t waves_x;       // waves per workgroup: waves_x x (4 / waves_x)
+    int32_t unroll;        // samples between early-termination checks
+    int32_t tiles_x, tiles_y;
+    int32_t tile_begin;    // first tile index of this job in the batch
+    int32_t pad0;
+    float* out;            // device RGBA32F image
+    int32_t* out_samples;  // device per-pixel sample counts or null
+    DevSource src[kMaxSources];
+};
+
+// Launch entry points implemented in raycast.hip.
+struct LaunchArgs {
+    const DevJob* jobs;        // device
+    int n_jobs;
+    int total_tiles;
+    const float* tf_pool;      // device, [slot][256][4]
+    int* cursor;               // device work counter (persistent mode)
+    int persistent;            // 0: one workgroup per tile; 1: grid-stride over a tile queue
+    int grid;                  // workgroups launched in persistent mode
+    int max_src;               // widest job's active source count (sizes the LDS tables)
+};
+
+int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t
+int launch_reset_counter(int* counter, void* stream);
+int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, void* dst,
+                        const int64_t* dst_stride, int esize, int f_dim, const int32_t lo[3],
+                        const int32_t ext[3], void* stream);
+int raycast_occupancy(int* blocks_per_cu);
+
+}  // namespace isaac

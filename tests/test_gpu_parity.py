@@ -1,0 +1,253 @@
+"""GPU parity: the HIP ray caster against the FP64 oracle, through the C ABI.
+
+Every image is compared channel by channel with the oracle (2e-3 plus the
+oracle's allowance for decisions within the margin); sample counts are
+compared exactly in runs without early termination.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from oracle.oracle import NO_TERMINATION
+from parity import compare, log, pixel_list
+from scenes import configs, fields, make_source, relayout
+from scenes.layout import Scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1611_09048_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(device=0)
+    yield c
+    c.close()
+
+
+def gpu_render(ctx, scene, **kw):
+    from paper_1611_09048_amd import device
+    log("gpu render:", scene.label or scene.dims, scene.width, "x", scene.height, kw)
+    img, cnt = device.render_scene(ctx, scene, **kw)
+    return img, cnt
+
+
+def full_parity(ctx, scene, label, counts=True):
+    img, cnt = gpu_render(ctx, scene)
+    rec = oracle.render(scene)
+    compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=label)
+    if counts:
+        img2, cnt2 = gpu_render(ctx, scene, ert_threshold=NO_TERMINATION)
+        rec2 = oracle.render(scene, ert_threshold=NO_TERMINATION)
+        compare(img2.reshape(-1, 4), cnt2.reshape(-1), rec2, label=label + " no-termination")
+    return img, cnt, rec
+
+
+def test_plain_scalar_full_size(ctx):
+    """One scalar, 64^3, nearest, 256x256 (the full plain-caster workload)."""
+    sc = configs.plain_scalar()
+    _, _, rec = full_parity(ctx, sc, "plain_scalar")
+    assert rec["samples"].sum() > 5e5
+
+
+@pytest.mark.parametrize("direction", [configs.D0, (-1.0, 0.0, 0.0), (0.3, -0.9, -0.4), (0.0, 0.0, 1.0)])
+def test_pic3_small(ctx, direction):
+    """Three sources, trilinear, two clip planes; 48^3, 300x170 (ragged against every tile shape)."""
+    sc = configs.pic3(n=48, width=300, height=170, direction=direction)
+    full_parity(ctx, sc, f"pic3 48^3 dir={direction}")
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_pic3_reduced_precision_storage(ctx, dtype):
+    """FP16/BF16 storage: parity against the oracle on the stored values; error vs FP32 reported."""
+    sc = configs.pic3(n=48, width=300, height=170, dtype=dtype)
+    img, cnt, rec = full_parity(ctx, sc, f"pic3 48^3 {dtype}")
+    ref32 = oracle.render(configs.pic3(n=48, width=300, height=170, dtype="f32"))
+    d = np.abs(img.reshape(-1, 4).astype(np.float64) - ref32["rgba"])
+    log(f"{dtype} storage vs FP32-field oracle: max {d.max(axis=0).tolist()} rms {np.sqrt((d ** 2).mean(axis=0)).tolist()}")
+
+
+@pytest.mark.parametrize("chunk", range(4))
+def test_random_small_scenes(ctx, chunk):
+    """Random tiny scenes covering every feature (layouts, dtypes, chains, clips, cameras, thresholds)."""
+    for seed in range(chunk * 15, chunk * 15 + 15):
+        sc = configs.random_small_scene(seed)
+        img, cnt = gpu_render(ctx, sc)
+        rec = oracle.render(sc)
+        compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=f"random_small[{seed}]")
+        img2, cnt2 = gpu_render(ctx, sc, ert_threshold=NO_TERMINATION)
+        rec2 = oracle.render(sc, ert_threshold=NO_TERMINATION)
+        compare(img2.reshape(-1, 4), cnt2.reshape(-1), rec2, label=f"random_small[{seed}] no-termination")
+
+
+def test_pic3_full_size_sampled(ctx):
+    """256^3, three sources, 1920x1080 in the benchmark's launch configuration; sampled pixels."""
+    sc = configs.pic3()
+    img, cnt = gpu_render(ctx, sc)
+    rng = np.random.default_rng(0)
+    px = pixel_list(sc.height, sc.width, 1500, rng, extra_rows=(540,), extra_cols=(960,),
+                    hit_mask=img[..., 3] > 0, n_hit=2500)
+    rec = oracle.render_pixels(sc, px)
+    g = img[px[:, 1], px[:, 0]]
+    c = cnt[px[:, 1], px[:, 0]]
+    stats = compare(g, c, rec, label="pic3 256^3 1080p sampled")
+    assert stats["samples"] > 1e5
+    # image outside the sampled set: finite and in range
+    assert np.isfinite(img).all() and img.min() >= 0.0 and img.max() <= 1.0 + 1e-6
+
+
+def test_closed_form_slab_on_gpu(ctx):
+    """The constant-42 source behind add(-41.5), constant TF (a=0.1): A = 1 - 0.9^16 exactly in closed form."""
+    dims = (8, 6, 5)
+    src = make_source("const42", fields.constant(dims, 0, 42.0), guard=0, chain="add(-41.5)",
+                      tf=configs.constant_tf((0.2, 0.6, 0.9), 0.1))
+    cam = configs.axis_camera(dims, axis=0, width=9, height=7, ortho_height=9.0)
+    for interp in (0, 1):
+        sc = Scene(dims=dims, sources=[src], camera=cam, width=9, height=7, step=0.5, interpolation=interp,
+                   ert_threshold=NO_TERMINATION)
+        img, cnt = gpu_render(ctx, sc)
+        hit = cnt > 0
+        assert np.array_equal(hit, pins._hit_mask(sc))
+        assert np.all(cnt[hit] == 16)
+        A = 1.0 - 0.9 ** 16
+        assert np.allclose(img[hit][:, 3], A, atol=2e-6)
+        assert np.allclose(img[hit][:, :3], np.array([0.2, 0.6, 0.9]) * A, atol=2e-6)
+        assert np.all(img[~hit] == 0.0)
+
+
+def _pic3_variant(sc, **src_changes):
+    srcs = [dataclasses.replace(s, **src_changes) for s in sc.sources]
+    return sc.with_(sources=srcs)
+
+
+def test_layout_invariance_bitwise(ctx):
+    """AoS, SoA, padded pitch, permuted and reversed axes give the same image bit for bit."""
+    sc = configs.pic3(n=32, width=160, height=96)
+    ref, refc = gpu_render(ctx, sc)
+    layouts = [dict(layout="soa"), dict(order=(2, 0, 1)), dict(flip=(True, False, True)),
+               dict(layout="soa", order=(1, 2, 0), flip=(False, True, False), pitch_align=4),
+               dict(pitch_align=1024)]
+    for lk in layouts:
+        s2 = sc.with_(sources=[relayout(s, **lk) for s in sc.sources])
+        img, cnt = gpu_render(ctx, s2)
+        assert np.array_equal(img, ref), lk
+        assert np.array_equal(cnt, refc), lk
+
+
+def test_disabled_and_zero_weight_sources(ctx):
+    """A disabled source (even with NULL data) and a zero-weight source equal the source being absent."""
+    sc = configs.pic3(n=32, width=120, height=80)
+    absent = sc.with_(sources=sc.sources[:2])
+    ref, _ = gpu_render(ctx, absent)
+    disabled = sc.with_(sources=sc.sources[:2] + [dataclasses.replace(sc.sources[2], enabled=False)])
+    img, _ = gpu_render(ctx, disabled)
+    assert np.array_equal(img, ref)
+    zero = sc.with_(sources=sc.sources[:2] + [dataclasses.replace(sc.sources[2], weight=0.0)])
+    img, _ = gpu_render(ctx, zero)
+    assert np.array_equal(img, ref)
+    # disabled with NULL component pointers
+    from paper_1611_09048_amd import device
+    import torch
+    vol = device.upload_volume(ctx, absent, 0)
+    descs = list(vol.descs)
+    from paper_1611_09048_amd import binding
+    descs.append(binding.source_desc(name="null", f_dim=3, dtype="f32", comp=[0, 0, 0], stride=(12, 0, 0), guard=1,
+                                     enabled=False))
+    ctx.set_sources(0, absent.dims, descs)
+    for k, s in enumerate(absent.sources):
+        ctx.set_transfer(0, k, s.tf)
+    out = device.new_image(absent)
+    ctx.render([device.render_job(absent, 0, out)])
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
+def test_guard_poison_never_reaches_image(ctx):
+    """NaN just outside the declared guard (and in an undeclared guard) never reaches a pixel."""
+    rng = np.random.default_rng(21)
+    dims = (20, 17, 23)
+    vals = fields.uniform_random(rng, dims, 1, 3, -0.5, 0.5)
+    tf = configs.random_tf(rng, 6, 0.2)
+    base = make_source("v", vals, guard=1, chain="length", tf=tf)
+    poisoned = make_source("v", vals, guard=1, chain="length", tf=tf, extra_layers=2)
+    cam = configs.orbit_camera(dims, (0.7, -0.2, 0.5), 1.2, 70.0)
+    sc = Scene(dims=dims, sources=[base], camera=cam, width=64, height=48, interpolation=1)
+    a, _ = gpu_render(ctx, sc)
+    b, _ = gpu_render(ctx, sc.with_(sources=[poisoned]))
+    assert np.isfinite(b).all() and np.array_equal(a, b)
+    # declared guard 0 over a NaN layer: clamps to the border instead of reading it
+    g0 = make_source("v", vals[1:-1, 1:-1, 1:-1], guard=0, chain="length", tf=tf, extra_layers=1)
+    inner = make_source("v", vals[1:-1, 1:-1, 1:-1], guard=0, chain="length", tf=tf)
+    c, _ = gpu_render(ctx, sc.with_(sources=[g0]))
+    d, _ = gpu_render(ctx, sc.with_(sources=[inner]))
+    assert np.isfinite(c).all() and np.array_equal(c, d)
+
+
+def test_fp16_exact_values_bitwise(ctx):
+    """Values exactly representable in FP16 render bit-identically from FP16 and FP32 storage."""
+    rng = np.random.default_rng(8)
+    dims = (24, 20, 18)
+    v = (rng.integers(0, 256, size=(dims[2] + 2, dims[1] + 2, dims[0] + 2, 3)) / 256.0).astype(np.float32)
+    tf = configs.random_tf(rng, 6, 0.1)
+    cam = configs.orbit_camera(dims, (0.4, 1.0, -0.3))
+    for dt in ("f16", "bf16"):
+        a = make_source("v", v, guard=1, chain="length | mul(0.7)", tf=tf)
+        b = make_source("v", v, dtype=dt, guard=1, chain="length | mul(0.7)", tf=tf)
+        sc = Scene(dims=dims, sources=[a], camera=cam, width=80, height=64, interpolation=1)
+        ia, _ = gpu_render(ctx, sc)
+        ib, _ = gpu_render(ctx, sc.with_(sources=[b]))
+        assert np.array_equal(ia, ib), dt
+
+
+def test_early_termination_bound(ctx):
+    """Stopping at theta moves a channel by at most 1 - theta (plus FP32 rounding)."""
+    sc = configs.pic3(n=40, width=128, height=96)
+    srcs = [dataclasses.replace(s, tf=[(x, r, g, b, min(1.0, 8 * a)) for (x, r, g, b, a) in s.tf])
+            for s in sc.sources]
+    sc = sc.with_(sources=srcs)
+    full, _ = gpu_render(ctx, sc, ert_threshold=NO_TERMINATION)
+    for theta in (0.999, 0.99, 0.9):
+        cut, _ = gpu_render(ctx, sc, ert_threshold=theta)
+        assert np.all(np.abs(cut.astype(np.float64) - full) <= (1.0 - theta) + 1e-5), theta
+
+
+def test_tile_shapes_give_identical_images(ctx):
+    sc = configs.pic3(n=32, width=203, height=77)
+    ref, refc = gpu_render(ctx, sc)
+    cls = 8                                  # size class of a 203-wide image: ceil(log2(203))
+    try:
+        for ww, wx in ((16, 2), (32, 1), (64, 4), (8, 4)):
+            ctx.set_tile_shape(cls, ww, wx, 1)
+            img, cnt = gpu_render(ctx, sc)
+            assert np.array_equal(img, ref) and np.array_equal(cnt, refc), (ww, wx)
+    finally:
+        ctx.set_tile_shape(cls, 8, 2, 1)
+
+
+def test_tiny_and_ragged_images(ctx):
+    base = configs.pic3(n=16, width=1, height=1)
+    for w, h in ((1, 1), (1, 37), (53, 1), (17, 3), (65, 65)):
+        sc = base.with_(width=w, height=h)
+        img, cnt = gpu_render(ctx, sc)
+        rec = oracle.render(sc)
+        compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=f"ragged {w}x{h}")
+
+
+def test_mirror_symmetry(ctx):
+    """A field mirror-symmetric in y seen from the mirror plane gives a left-right mirrored image."""
+    rng = np.random.default_rng(5)
+    half = fields.uniform_random(rng, (31, 12, 26), 1, 1, 0.0, 1.0)
+    v = np.concatenate([half, half[:, ::-1, :]], axis=1)
+    dims = (31, 24, 26)
+    src = make_source("m", v, guard=1, tf=configs.random_tf(rng, 5, 0.2))
+    from scenes import Camera
+    cam = Camera(eye=(-40.0, 12.0, 30.0), center=(15.5, 12.0, 13.0), up=(0.0, 0.0, 1.0), fovy_deg=45.0)
+    sc = Scene(dims=dims, sources=[src], camera=cam, width=100, height=70, interpolation=1)
+    img, _ = gpu_render(ctx, sc)
+    assert img[..., 3].max() > 0.05
+    assert np.allclose(img, img[:, ::-1], atol=2e-3)
