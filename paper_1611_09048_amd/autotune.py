@@ -1,0 +1,96 @@
+"""Autotuner for the ray-tile shape and sample schedule of each image-size class.
+
+For every size class present in a workload it times the ray-casting kernel
+(HIP events around the launch, ISAAC_TIMING) for each candidate
+(wave_w, waves_x, unroll) and keeps the fastest.  Results are cached as JSON
+keyed by device architecture, size class and a source signature (source
+count, storage types, feature dimensions, interpolation), and applied with
+isaac_set_tile_shape.  Tile shape and schedule never change an image: every
+candidate produces the same pixels bit for bit.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+from . import binding
+
+WAVE_W = (8, 16, 32, 64)
+WAVES_X = (1, 2, 4)
+UNROLL = (1, 2, 4)
+DEFAULT = (8, 2, 1)
+
+
+def size_class(width: int, height: int) -> int:
+    m = max(width, height)
+    return min(15, max(0, math.ceil(math.log2(m)) if m > 1 else 0))
+
+
+def candidates(unrolls: Sequence[int] = UNROLL) -> List[Tuple[int, int, int]]:
+    return [(w, x, u) for w in WAVE_W for x in WAVES_X for u in unrolls]
+
+
+def signature(scene) -> str:
+    parts = [f"{s.dtype}x{s.f_dim}" for s in scene.sources if s.enabled]
+    return f"{'tri' if scene.interpolation else 'near'}:" + ",".join(parts)
+
+
+def cache_key(arch: str, cls: int, sig: str) -> str:
+    return f"{arch}|{cls}|{sig}"
+
+
+def load_cache(path: str) -> Dict[str, list]:
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        data = json.load(f)
+    return {k: list(v) for k, v in data.items()}
+
+
+def save_cache(path: str, table: Dict[str, list]) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def pick(times: Dict[Tuple[int, int, int], float]) -> Tuple[int, int, int]:
+    """Fastest candidate; ties go to the earlier (smaller) shape."""
+    return min(sorted(times), key=lambda c: times[c])
+
+
+def time_candidate(ctx: binding.Context, jobs: Sequence[binding.RenderDesc], cls: int,
+                   cand: Tuple[int, int, int], reps: int = 3, flags: int = 0) -> float:
+    ctx.set_tile_shape(cls, *cand)
+    ctx.render(list(jobs), flags)               # warm-up (and graph capture for batches)
+    ctx.timing()
+    for _ in range(reps):
+        ctx.render(list(jobs), flags | binding.TIMING)
+    ms, n = ctx.timing()
+    return ms / max(n, 1)
+
+
+def tune(ctx: binding.Context, jobs_by_class: Dict[int, Sequence[binding.RenderDesc]], arch: str = "gfx950",
+         sig: str = "", cands: Optional[Iterable[Tuple[int, int, int]]] = None, reps: int = 3,
+         cache: Optional[Dict[str, list]] = None, flags: int = 0, log=None) -> Dict[int, Tuple[int, int, int]]:
+    """Tune each size class on its jobs; returns {class: (wave_w, waves_x, unroll)} and applies it."""
+    cands = list(cands) if cands is not None else candidates()
+    best = {}
+    for cls, jobs in sorted(jobs_by_class.items()):
+        key = cache_key(arch, cls, sig)
+        if cache is not None and key in cache:
+            best[cls] = tuple(cache[key])
+            ctx.set_tile_shape(cls, *best[cls])
+            continue
+        times = {c: time_candidate(ctx, jobs, cls, c, reps, flags) for c in cands}
+        best[cls] = pick(times)
+        if log:
+            log(f"autotune class {cls}: best {best[cls]} {times[best[cls]]:.4f} ms "
+                f"(default {times.get(DEFAULT, float('nan')):.4f} ms)")
+        ctx.set_tile_shape(cls, *best[cls])
+        if cache is not None:
+            cache[key] = list(best[cls])
+    return best

@@ -26,8 +26,14 @@ namespace {
 
 constexpr int kRsrcFlags = 0x00020000;   // raw buffer, 32-bit data format (gfx9 family)
 
+// Source descriptors are wave-uniform by construction; readfirstlane keeps
+// the buffer resource in SGPRs whatever the compiler could prove.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(uint64_t base, uint32_t n) {
-    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(base), (short)0, (int)n, kRsrcFlags);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    const uint64_t b = ((uint64_t)hi << 32) | lo;
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(b), (short)0,
+                                             (int)__builtin_amdgcn_readfirstlane(n), kRsrcFlags);
 }
 
 __device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, int off) {
@@ -41,49 +47,56 @@ __device__ __forceinline__ float ld_scalar(__amdgpu_buffer_rsrc_t r, int off, in
     return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
-// Components of one voxel, converted to FP32.  `off` is the byte offset of
-// the voxel relative to component 0 of voxel (0,0,0).
-struct Vec4 {
-    float v[4];
-};
-
-__device__ __forceinline__ Vec4 fetch(const DevSource& S, int off) {
-    Vec4 out = {{0.f, 0.f, 0.f, 0.f}};
+// N voxels of one source (N = 1 nearest, 8 trilinear corners); off[i] is the
+// byte offset of voxel i relative to voxel (0,0,0).  One uniform branch per
+// call selects the load form, and all N loads are issued before any is used.
+template <int N>
+__device__ __forceinline__ void fetch(const DevSource& S, const int (&off)[N], float (&v)[N][4]) {
     const int f_dim = S.f_dim;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i][0] = v[i][1] = v[i][2] = v[i][3] = 0.f;
     if (S.packed && S.dtype == DT_F32) {
+        // adjacent FP32 components: consecutive dword loads merge into x2/x3/x4 loads
         const __amdgpu_buffer_rsrc_t r = make_rsrc(S.base[0], S.num_records[0]);
-        const int o = off + S.comp_off[0];
+        const int o = S.comp_off[0];
         if (f_dim == 1) {
-            out.v[0] = ld_f32(r, o);
-        } else if (f_dim == 2) {
-            auto w = __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0);
-            out.v[0] = __builtin_bit_cast(float, w[0]);
-            out.v[1] = __builtin_bit_cast(float, w[1]);
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i][0] = ld_f32(r, off[i] + o);
         } else if (f_dim == 3) {
-            auto w = __builtin_amdgcn_raw_buffer_load_b96(r, o, 0, 0);
-            out.v[0] = __builtin_bit_cast(float, w[0]);
-            out.v[1] = __builtin_bit_cast(float, w[1]);
-            out.v[2] = __builtin_bit_cast(float, w[2]);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                v[i][0] = ld_f32(r, off[i] + o);
+                v[i][1] = ld_f32(r, off[i] + o + 4);
+                v[i][2] = ld_f32(r, off[i] + o + 8);
+            }
+        } else if (f_dim == 2) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                v[i][0] = ld_f32(r, off[i] + o);
+                v[i][1] = ld_f32(r, off[i] + o + 4);
+            }
         } else {
-            auto w = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
-            out.v[0] = __builtin_bit_cast(float, w[0]);
-            out.v[1] = __builtin_bit_cast(float, w[1]);
-            out.v[2] = __builtin_bit_cast(float, w[2]);
-            out.v[3] = __builtin_bit_cast(float, w[3]);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                v[i][0] = ld_f32(r, off[i] + o);
+                v[i][1] = ld_f32(r, off[i] + o + 4);
+                v[i][2] = ld_f32(r, off[i] + o + 8);
+                v[i][3] = ld_f32(r, off[i] + o + 12);
+            }
         }
-        return out;
+        return;
     }
-    if (S.packed) {
-        const __amdgpu_buffer_rsrc_t r = make_rsrc(S.base[0], S.num_records[0]);
+    const int dtype = S.dtype;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < f_dim) out.v[c] = ld_scalar(r, off + S.comp_off[c], S.dtype);
-        return out;
+    for (int c = 0; c < 4; ++c) {
+        if (c < f_dim) {
+            const int k = S.packed ? 0 : c;
+            const __amdgpu_buffer_rsrc_t r = make_rsrc(S.base[k], S.num_records[k]);
+            const int o = S.comp_off[c];
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i][c] = ld_scalar(r, off[i] + o, dtype);
+        }
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        if (c < f_dim) out.v[c] = ld_scalar(make_rsrc(S.base[c], S.num_records[c]), off + S.comp_off[c], S.dtype);
-    return out;
 }
 
 // pow for FP32 with IEEE special cases: exp2(y log2|x|), a negative base
@@ -107,59 +120,84 @@ __device__ __forceinline__ float pow_f32(float x, float y) {
     return r;
 }
 
-__device__ __forceinline__ float run_chain(const DevSource& S, Vec4 x) {
-    float* v = x.v;
+// Functor chain over N dates at once: one wave-uniform dispatch per functor,
+// N dates of work inside.  res[i] is component 0 of date i's result.
+template <int N>
+__device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], float (&res)[N]) {
     const int n_ops = S.n_ops;
     for (int o = 0; o < n_ops; ++o) {
         const DevOp& op = S.ops[o];
         const int dim = op.dim;
+        const float a[4] = {op.arg[0], op.arg[1], op.arg[2], op.arg[3]};
         switch (op.kind) {
         case OP_ADD:
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if (c < dim) v[c] = v[c] + op.arg[c];
+                if (c < dim)
+#pragma unroll
+                    for (int i = 0; i < N; ++i) v[i][c] = v[i][c] + a[c];
             break;
         case OP_MUL:
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if (c < dim) v[c] = v[c] * op.arg[c];
+                if (c < dim)
+#pragma unroll
+                    for (int i = 0; i < N; ++i) v[i][c] = v[i][c] * a[c];
             break;
         case OP_POW:
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if (c < dim) v[c] = pow_f32(v[c], op.arg[c]);
+                if (c < dim)
+#pragma unroll
+                    for (int i = 0; i < N; ++i) v[i][c] = pow_f32(v[i][c], a[c]);
             break;
         case OP_SQRT:
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if (c < dim) v[c] = v[c] < 0.f ? __builtin_nanf("") : __builtin_amdgcn_sqrtf(v[c]);
+                if (c < dim)
+#pragma unroll
+                    for (int i = 0; i < N; ++i)
+                        v[i][c] = v[i][c] < 0.f ? __builtin_nanf("") : __builtin_amdgcn_sqrtf(v[i][c]);
             break;
         case OP_SQUARE:
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if (c < dim) v[c] = v[c] * v[c];
-            break;
-        case OP_LENGTH: {
-            float s = v[0] * v[0];
+                if (c < dim)
 #pragma unroll
-            for (int c = 1; c < 4; ++c)
-                if (c < dim) s = fmaf(v[c], v[c], s);
-            v[0] = __builtin_amdgcn_sqrtf(s);
+                    for (int i = 0; i < N; ++i) v[i][c] = v[i][c] * v[i][c];
             break;
-        }
-        case OP_SUM: {
-            float s = v[0];
+        case OP_LENGTH:
+            if (dim == 3) {
 #pragma unroll
-            for (int c = 1; c < 4; ++c)
-                if (c < dim) s = s + v[c];
-            v[0] = s;
+                for (int i = 0; i < N; ++i)
+                    v[i][0] = __builtin_amdgcn_sqrtf(fmaf(v[i][2], v[i][2], fmaf(v[i][1], v[i][1], v[i][0] * v[i][0])));
+            } else {
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    float s = v[i][0] * v[i][0];
+                    if (dim > 1) s = fmaf(v[i][1], v[i][1], s);
+                    if (dim > 2) s = fmaf(v[i][2], v[i][2], s);
+                    if (dim > 3) s = fmaf(v[i][3], v[i][3], s);
+                    v[i][0] = __builtin_amdgcn_sqrtf(s);
+                }
+            }
             break;
-        }
+        case OP_SUM:
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                float s = v[i][0];
+                if (dim > 1) s = s + v[i][1];
+                if (dim > 2) s = s + v[i][2];
+                if (dim > 3) s = s + v[i][3];
+                v[i][0] = s;
+            }
+            break;
         default:
             break;
         }
     }
-    return v[0];
+#pragma unroll
+    for (int i = 0; i < N; ++i) res[i] = v[i][0];
 }
 
 // Transfer-table lookup: clamp to [0,1] (NaN -> 0), 255 intervals, linear.
@@ -185,7 +223,7 @@ struct RaySetup {
     int kb, ke;
 };
 
-__device__ bool setup_ray(const DevJob& J, int px, int py, RaySetup& R) {
+__device__ __forceinline__ bool setup_ray(const DevJob& J, int px, int py, RaySetup& R) {
 #pragma clang fp contract(off)
     const double x = (2.0 * (px + 0.5) / J.width - 1.0) * J.h * J.aspect;
     const double y = (1.0 - 2.0 * (py + 0.5) / J.height) * J.h;
@@ -270,15 +308,19 @@ __device__ bool setup_ray(const DevJob& J, int px, int py, RaySetup& R) {
     return true;
 }
 
-// One source at position p: nearest cell or trilinear over chain outputs.
+// One source at position p: nearest cell, or trilinear over the chain
+// outputs of the 8 surrounding voxels (chain per fetched voxel, then blend).
 template <int INTERP>
 __device__ __forceinline__ float sample_source(const DevSource& S, const int dims[3], const float p[3]) {
     if (INTERP == 0) {
         const int qx = clampi((int)floorf(p[0]), 0, dims[0] - 1);
         const int qy = clampi((int)floorf(p[1]), 0, dims[1] - 1);
         const int qz = clampi((int)floorf(p[2]), 0, dims[2] - 1);
-        const int off = qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2];
-        return run_chain(S, fetch(S, off));
+        const int off[1] = {qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2]};
+        float v[1][4], r[1];
+        fetch<1>(S, off, v);
+        run_chain<1>(S, v, r);
+        return r[0];
     }
     int i0[3], i1[3];
     float w[3];
@@ -297,25 +339,22 @@ __device__ __forceinline__ float sample_source(const DevSource& S, const int dim
     const int x0 = i0[0] * S.stride[0], x1 = i1[0] * S.stride[0];
     const int y0 = i0[1] * S.stride[1], y1 = i1[1] * S.stride[1];
     const int z0 = i0[2] * S.stride[2], z1 = i1[2] * S.stride[2];
-    const float c000 = run_chain(S, fetch(S, x0 + y0 + z0));
-    const float c100 = run_chain(S, fetch(S, x1 + y0 + z0));
-    const float c010 = run_chain(S, fetch(S, x0 + y1 + z0));
-    const float c110 = run_chain(S, fetch(S, x1 + y1 + z0));
-    const float c001 = run_chain(S, fetch(S, x0 + y0 + z1));
-    const float c101 = run_chain(S, fetch(S, x1 + y0 + z1));
-    const float c011 = run_chain(S, fetch(S, x0 + y1 + z1));
-    const float c111 = run_chain(S, fetch(S, x1 + y1 + z1));
-    const float c00 = fmaf(w[0], c100 - c000, c000);
-    const float c10 = fmaf(w[0], c110 - c010, c010);
-    const float c01 = fmaf(w[0], c101 - c001, c001);
-    const float c11 = fmaf(w[0], c111 - c011, c011);
+    const int off[8] = {x0 + y0 + z0, x1 + y0 + z0, x0 + y1 + z0, x1 + y1 + z0,
+                        x0 + y0 + z1, x1 + y0 + z1, x0 + y1 + z1, x1 + y1 + z1};
+    float v[8][4], c[8];
+    fetch<8>(S, off, v);
+    run_chain<8>(S, v, c);
+    const float c00 = fmaf(w[0], c[1] - c[0], c[0]);
+    const float c10 = fmaf(w[0], c[3] - c[2], c[2]);
+    const float c01 = fmaf(w[0], c[5] - c[4], c[4]);
+    const float c11 = fmaf(w[0], c[7] - c[6], c[6]);
     const float c0 = fmaf(w[1], c10 - c00, c00);
     const float c1 = fmaf(w[1], c11 - c01, c01);
     return fmaf(w[2], c1 - c0, c0);
 }
 
 template <int INTERP>
-__device__ void march(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R, float4& out,
+__device__ __forceinline__ void march(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R, float4& out,
                       int& count) {
     const float step = (float)J.step;
     const float ert = J.ert;
@@ -356,13 +395,6 @@ __device__ void march(const DevJob& J, const float4* __restrict__ s_tf, const Ra
     count = n;
 }
 
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-    // consecutive tiles to one XCD: workgroup b runs on XCD b % 8
-    const int q = n / 8, r = n % 8;
-    const int x = b % 8, i = b / 8;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-}
-
 __device__ __forceinline__ int find_job(const DevJob* __restrict__ jobs, int n_jobs, int tile) {
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -373,7 +405,7 @@ __device__ __forceinline__ int find_job(const DevJob* __restrict__ jobs, int n_j
     return lo;
 }
 
-__device__ void render_tile(const DevJob& J, int t, const float4* __restrict__ s_tf) {
+__device__ __forceinline__ void render_tile(const DevJob& J, int t, const float4* __restrict__ s_tf) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ww = J.wave_w, wh = 64 / ww;
     const int gx = J.waves_x, gy = 4 / gx;
@@ -393,31 +425,34 @@ __device__ void render_tile(const DevJob& J, int t, const float4* __restrict__ s
     if (J.out_samples) J.out_samples[pix] = count;
 }
 
-__global__ __launch_bounds__(kBlockThreads) void raycast_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(kBlockThreads) void raycast_kernel(const DevJob* __restrict__ jobs,
+                                                                 const float4* __restrict__ tf_pool,
+                                                                 int* __restrict__ cursor, int n_jobs,
+                                                                 int total_tiles, int persistent) {
     extern __shared__ float4 s_tf[];
     __shared__ int s_tile;
     int cur_job = -1;
     for (int iter = 0;; ++iter) {
         int tile;
-        if (a.persistent) {
-            if (threadIdx.x == 0) s_tile = atomicAdd(a.cursor, 1);
+        if (persistent) {
+            if (threadIdx.x == 0) s_tile = atomicAdd(cursor, 1);
             __syncthreads();
             tile = s_tile;
             __syncthreads();
-            if (tile >= a.total_tiles) break;
+            if (tile >= total_tiles) break;
         } else {
             if (iter > 0) break;
-            tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+            tile = (int)blockIdx.x;
         }
         tile = __builtin_amdgcn_readfirstlane(tile);
-        const int job = __builtin_amdgcn_readfirstlane(find_job(a.jobs, a.n_jobs, tile));
-        const DevJob& J = a.jobs[job];
+        const int job = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, tile));
+        const DevJob& J = jobs[job];
         if (job != cur_job) {
             __syncthreads();
             const int n = J.n_src * kTfEntries;
             for (int i = threadIdx.x; i < n; i += kBlockThreads) {
                 const int s = i / kTfEntries, e = i % kTfEntries;
-                s_tf[i] = reinterpret_cast<const float4*>(a.tf_pool)[(size_t)J.src[s].tf_slot * kTfEntries + e];
+                s_tf[i] = tf_pool[(size_t)J.src[s].tf_slot * kTfEntries + e];
             }
             __syncthreads();
             cur_job = job;
@@ -464,7 +499,8 @@ int launch_raycast(const LaunchArgs& a, void* stream) {
     const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfEntries * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(raycast_kernel, dim3(blocks), dim3(kBlockThreads), lds, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(raycast_kernel, dim3(blocks), dim3(kBlockThreads), lds, (hipStream_t)stream, a.jobs,
+                       reinterpret_cast<const float4*>(a.tf_pool), a.cursor, a.n_jobs, a.total_tiles, a.persistent);
     return hipGetLastError();
 }
 

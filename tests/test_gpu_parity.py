@@ -241,9 +241,10 @@ def test_tiny_and_ragged_images(ctx):
 def test_mirror_symmetry(ctx):
     """A field mirror-symmetric in y seen from the mirror plane gives a left-right mirrored image."""
     rng = np.random.default_rng(5)
-    half = fields.uniform_random(rng, (31, 12, 26), 1, 1, 0.0, 1.0)
-    v = np.concatenate([half, half[:, ::-1, :]], axis=1)
     dims = (31, 24, 26)
+    # rows y = -1..11 (guard included), mirrored onto y = 12..24 about the plane y = 12
+    half = rng.uniform(0.0, 1.0, size=(dims[2] + 2, 13, dims[0] + 2)).astype(np.float32)
+    v = np.concatenate([half, half[:, ::-1, :]], axis=1)
     src = make_source("m", v, guard=1, tf=configs.random_tf(rng, 5, 0.2))
     from scenes import Camera
     cam = Camera(eye=(-40.0, 12.0, 30.0), center=(15.5, 12.0, 13.0), up=(0.0, 0.0, 1.0), fovy_deg=45.0)
