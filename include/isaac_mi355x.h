@@ -173,13 +173,28 @@ isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int
  * last call (waits for them), then resets. */
 isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count);
 
-/* Ray-tile shape for jobs of a given image-size class (autotuner output).
- * size_class = ceil(log2(max(width,height))) clamped to [0,15]; wave_w in
- * {8,16,32,64} (rays of one 64-wide wave are wave_w x 64/wave_w pixels);
- * waves_x in {1,2,4} (a 4-wave workgroup is waves_x x 4/waves_x waves);
- * unroll in {1,2,4}: samples per early-termination check. */
-isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w, int waves_x, int unroll);
-isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_w, int* waves_x, int* unroll);
+/* Ray-tile shape and scan-point schedule for jobs of one image-size class
+ * (the autotuner's output).  size_class = ceil(log2(max(width,height)))
+ * clamped to [0,15].
+ *   lanes_per_ray in {1,2,4,8,16}: lanes sharing one ray, each taking every
+ *     lanes_per_ray-th scan point (more parallelism where few rays meet the
+ *     volume); a 64-lane wave holds 64/lanes_per_ray rays;
+ *   wave_w, a power of two in [2, 64/lanes_per_ray]: a wave's rays form a
+ *     wave_w x (64/lanes_per_ray/wave_w) pixel block;
+ *   waves_x in {1,2,4}: the 4 waves of a workgroup are waves_x x 4/waves_x;
+ *   unroll in {1,2} (one lane per ray only): scan points whose source reads
+ *     are issued together;
+ *   min_waves in {0,4}: 4 selects the kernel variant compiled to keep at
+ *     least 4 waves resident per SIMD (not with lanes_per_ray 2 or unroll 2).
+ * Jobs batched into one launch share its lanes_per_ray, unroll and min_waves.
+ * Defaults: (8, 2, 1, 1, 0).  Settings with one lane per ray give the same
+ * image bit for bit; more lanes composite each row of scan points by a scan,
+ * which changes only FP32 rounding; a given setting always reproduces its
+ * image bit for bit. */
+isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w, int waves_x, int unroll,
+                                  int lanes_per_ray, int min_waves);
+isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_w, int* waves_x, int* unroll,
+                                  int* lanes_per_ray, int* min_waves);
 
 /* ---- serving: library-owned output images admitted against mem_budget ---- */
 

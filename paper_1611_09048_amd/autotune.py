@@ -2,7 +2,7 @@
 
 For every size class present in a workload it times the ray-casting kernel
 (HIP events around the launch, ISAAC_TIMING) for each candidate
-(wave_w, waves_x, unroll) and keeps the fastest.  Results are cached as JSON
+(wave_w, waves_x, unroll, lanes_per_ray, min_waves) and keeps the fastest.  Results are cached as JSON
 keyed by device architecture, size class and a source signature (source
 count, storage types, feature dimensions, interpolation), and applied with
 isaac_set_tile_shape.  Tile shape and schedule never change an image: every
@@ -18,10 +18,12 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
 from . import binding
 
-WAVE_W = (8, 16, 32, 64)
+WAVE_W = (2, 4, 8, 16, 32, 64)
 WAVES_X = (1, 2, 4)
-UNROLL = (1, 2, 4)
-DEFAULT = (8, 2, 1)
+UNROLL = (1, 2)
+LANES = (1, 2, 4, 8, 16)
+MIN_WAVES = (0, 4)
+DEFAULT = (8, 2, 1, 1, 0)
 
 
 def size_class(width: int, height: int) -> int:
@@ -29,8 +31,20 @@ def size_class(width: int, height: int) -> int:
     return min(15, max(0, math.ceil(math.log2(m)) if m > 1 else 0))
 
 
-def candidates(unrolls: Sequence[int] = UNROLL) -> List[Tuple[int, int, int]]:
-    return [(w, x, u) for w in WAVE_W for x in WAVES_X for u in unrolls]
+def candidates(unrolls: Sequence[int] = UNROLL, lanes: Sequence[int] = LANES, wave_ws: Sequence[int] = WAVE_W,
+               waves_xs: Sequence[int] = WAVES_X, min_waves: Sequence[int] = MIN_WAVES) -> List[Tuple]:
+    """Valid (wave_w, waves_x, unroll, lanes_per_ray, min_waves) settings."""
+    out = []
+    for g in lanes:
+        for u in (unrolls if g == 1 else (1,)):
+            for m in min_waves:
+                if m and (g == 2 or u == 2):
+                    continue
+                for w in wave_ws:
+                    if w <= 64 // g and (w >= 8 or w == 64 // g):
+                        for x in waves_xs:
+                            out.append((w, x, u, g, m))
+    return out
 
 
 def signature(scene) -> str:
@@ -57,13 +71,13 @@ def save_cache(path: str, table: Dict[str, list]) -> None:
     os.replace(tmp, path)
 
 
-def pick(times: Dict[Tuple[int, int, int], float]) -> Tuple[int, int, int]:
+def pick(times: Dict[Tuple, float]) -> Tuple:
     """Fastest candidate; ties go to the earlier (smaller) shape."""
     return min(sorted(times), key=lambda c: times[c])
 
 
 def time_candidate(ctx: binding.Context, jobs: Sequence[binding.RenderDesc], cls: int,
-                   cand: Tuple[int, int, int], reps: int = 3, flags: int = 0) -> float:
+                   cand: Tuple, reps: int = 3, flags: int = 0) -> float:
     ctx.set_tile_shape(cls, *cand)
     ctx.render(list(jobs), flags)               # warm-up (and graph capture for batches)
     ctx.timing()
@@ -74,9 +88,9 @@ def time_candidate(ctx: binding.Context, jobs: Sequence[binding.RenderDesc], cls
 
 
 def tune(ctx: binding.Context, jobs_by_class: Dict[int, Sequence[binding.RenderDesc]], arch: str = "gfx950",
-         sig: str = "", cands: Optional[Iterable[Tuple[int, int, int]]] = None, reps: int = 3,
-         cache: Optional[Dict[str, list]] = None, flags: int = 0, log=None) -> Dict[int, Tuple[int, int, int]]:
-    """Tune each size class on its jobs; returns {class: (wave_w, waves_x, unroll)} and applies it."""
+         sig: str = "", cands: Optional[Iterable[Tuple]] = None, reps: int = 3,
+         cache: Optional[Dict[str, list]] = None, flags: int = 0, log=None) -> Dict[int, Tuple]:
+    """Tune each size class on its jobs; returns {class: (wave_w, waves_x, unroll, lanes_per_ray, min_waves)} and applies it."""
     cands = list(cands) if cands is not None else candidates()
     best = {}
     for cls, jobs in sorted(jobs_by_class.items()):

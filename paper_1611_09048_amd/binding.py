@@ -99,9 +99,8 @@ def load(path: Optional[str] = None):
     lib.isaac_release_transfer.argtypes = [c_ctx, ctypes.c_int32]
     lib.isaac_render.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.c_int, ctypes.c_uint]
     lib.isaac_timing.argtypes = [c_ctx, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
-    lib.isaac_set_tile_shape.argtypes = [c_ctx, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
-    lib.isaac_get_tile_shape.argtypes = [c_ctx, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
-                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.isaac_set_tile_shape.argtypes = [c_ctx] + [ctypes.c_int] * 6
+    lib.isaac_get_tile_shape.argtypes = [c_ctx, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 5
     lib.isaac_submit.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.POINTER(ctypes.c_uint64)]
     lib.isaac_submit_batch.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_uint64)]
@@ -201,13 +200,14 @@ class Context:
         self._check(self.lib.isaac_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
-    def set_tile_shape(self, size_class: int, wave_w: int, waves_x: int, unroll: int = 1):
-        self._check(self.lib.isaac_set_tile_shape(self.h, size_class, wave_w, waves_x, unroll))
+    def set_tile_shape(self, size_class: int, wave_w: int, waves_x: int, unroll: int = 1, lanes: int = 1,
+                       min_waves: int = 0):
+        self._check(self.lib.isaac_set_tile_shape(self.h, size_class, wave_w, waves_x, unroll, lanes, min_waves))
 
     def get_tile_shape(self, size_class: int):
-        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        self._check(self.lib.isaac_get_tile_shape(self.h, size_class, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+        v = [ctypes.c_int() for _ in range(5)]
+        self._check(self.lib.isaac_get_tile_shape(self.h, size_class, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     # -- serving ----------------------------------------------------------------
     def submit_batch(self, jobs: Sequence[RenderDesc]):

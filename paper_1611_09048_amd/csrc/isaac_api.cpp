@@ -228,7 +228,7 @@ struct RingSlot {
     // graph cache
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    int g_jobs = -1, g_tiles = -1, g_grid = -1, g_src = -1;
+    int g_jobs = -1, g_tiles = -1, g_grid = -1, g_src = -1, g_unroll = -1, g_lanes = -1, g_hint = -1;
 };
 
 struct Pending {
@@ -245,7 +245,7 @@ struct Ticket {
 };
 
 struct TileShape {
-    int wave_w = 8, waves_x = 2, unroll = 1;
+    int wave_w = 8, waves_x = 2, unroll = 1, lanes = 1, waves_hint = 0;
 };
 
 }  // namespace
@@ -456,6 +456,36 @@ bool camera_basis(const isaac_render_desc& j, CameraBasis& cb, std::string& err)
     return true;
 }
 
+// Which compile-time specialized loop (if any) fits the job's active sources.
+int32_t signature_of(const DevJob& dj) {
+    int kinds[kMaxSources];
+    for (int s = 0; s < dj.n_src; ++s) {
+        const DevSource& d = dj.src[s];
+        bool small = true;
+        for (int a = 0; a < 3; ++a) small = small && std::abs((int64_t)d.stride[a]) < (1 << 23);
+        if (!d.packed || !small || (d.f_dim != 1 && d.f_dim != 3)) return SIG_GENERIC;
+        kinds[s] = d.dtype * 2 + (d.f_dim == 3 ? 1 : 0);   // dtype-major: F32x1=0, F32x3=1, F16x1=2, ...
+    }
+    if (dj.n_src == 1 && kinds[0] == 0) return SIG_F32x1;
+    if (dj.n_src == 3 && kinds[1] == kinds[0] + 1 && kinds[2] == kinds[1] && kinds[0] % 2 == 0) {
+        if (kinds[0] == 0) return SIG_PIC3_F32;
+        if (kinds[0] == 2) return SIG_PIC3_F16;
+        if (kinds[0] == 4) return SIG_PIC3_BF16;
+    }
+    return SIG_GENERIC;
+}
+
+// Tile decomposition of a job for a launch running `lanes` lanes per ray.
+void set_tiles(DevJob& dj, int lanes, int unroll) {
+    dj.lanes = lanes;
+    dj.unroll = lanes > 1 ? 1 : unroll;
+    const int rays = 64 / lanes;
+    if (dj.wave_w > rays) dj.wave_w = rays;
+    const int tw = dj.wave_w * dj.waves_x, th = (rays / dj.wave_w) * (4 / dj.waves_x);
+    dj.tiles_x = (dj.width + tw - 1) / tw;
+    dj.tiles_y = (dj.height + th - 1) / th;
+}
+
 int size_class_of(int w, int h) {
     int m = std::max(w, h), c = 0;
     while ((1 << c) < m && c < 15) ++c;
@@ -527,9 +557,9 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
     dj.wave_w = ts.wave_w;
     dj.waves_x = ts.waves_x;
     dj.unroll = ts.unroll;
-    const int tw = ts.wave_w * ts.waves_x, th = (64 / ts.wave_w) * (4 / ts.waves_x);
-    dj.tiles_x = (j.width + tw - 1) / tw;
-    dj.tiles_y = (j.height + th - 1) / th;
+    dj.lanes = ts.lanes;
+    dj.waves_hint = ts.waves_hint;
+    set_tiles(dj, ts.lanes, ts.unroll);
     dj.out = j.out_rgba;
     dj.out_samples = j.out_samples;
     int n_act = 0;
@@ -562,6 +592,7 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
         ds.weight = w;
     }
     dj.n_src = n_act;
+    dj.sig = signature_of(dj);
     *n_active_out = n_act;
     return ISAAC_OK;
 }
@@ -623,11 +654,19 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     RingSlot* r = nullptr;
     isaac_status st = acquire_slot(ctx, &r);
     if (st) return st;
+    // one kernel variant per launch: the most lanes per ray any job asks for,
+    // else the deepest unroll; every job's tiles follow the launch's variant
+    int lanes = 1, unroll = 1, hint = 0;
+    for (const DevJob& dj : djs) lanes = std::max(lanes, (int)dj.lanes);
+    for (const DevJob& dj : djs) hint = std::max(hint, (int)dj.waves_hint);
+    if (lanes == 1)
+        for (const DevJob& dj : djs) unroll = std::max(unroll, (int)dj.unroll);
     int tiles = 0;
     for (int i = 0; i < n; ++i) {
         r->host[i] = djs[i];
+        set_tiles(r->host[i], lanes, unroll);
         r->host[i].tile_begin = tiles;
-        tiles += djs[i].tiles_x * djs[i].tiles_y;
+        tiles += r->host[i].tiles_x * r->host[i].tiles_y;
     }
     const uint64_t seq = ++ctx->seq;
     // mark every table read by this call
@@ -643,6 +682,9 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     la.persistent = n > 1 ? 1 : 0;
     la.grid = std::max(1, ctx->n_cu * ctx->blocks_per_cu);
     la.max_src = std::max(1, max_src);
+    la.unroll = unroll;
+    la.lanes = lanes;
+    la.waves_hint = (lanes == 2 || unroll > 1) ? 0 : hint;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (flags & ISAAC_TIMING) {
         t0 = get_event(ctx);
@@ -651,7 +693,8 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     }
     const bool use_graph = n > 1 && !(flags & ISAAC_NO_GRAPH);
     if (use_graph) {
-        if (!r->exec || r->g_jobs != n || r->g_tiles != tiles || r->g_grid != la.grid || r->g_src != la.max_src) {
+        if (!r->exec || r->g_jobs != n || r->g_tiles != tiles || r->g_grid != la.grid || r->g_src != la.max_src ||
+            r->g_unroll != la.unroll || r->g_lanes != la.lanes || r->g_hint != la.waves_hint) {
             if (r->exec) hipGraphExecDestroy(r->exec);
             if (r->graph) hipGraphDestroy(r->graph);
             r->exec = nullptr;
@@ -673,6 +716,9 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
             r->g_tiles = tiles;
             r->g_grid = la.grid;
             r->g_src = la.max_src;
+            r->g_unroll = la.unroll;
+            r->g_lanes = la.lanes;
+            r->g_hint = la.waves_hint;
         }
         if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
         HIP_TRY(ctx, hipGraphLaunch(r->exec, stream));
@@ -1019,20 +1065,29 @@ isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count) {
     return ISAAC_OK;
 }
 
-isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w, int waves_x, int unroll) {
+isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w, int waves_x, int unroll,
+                                  int lanes_per_ray, int min_waves) {
     if (!ctx) return ISAAC_ERR_INVALID_ARGUMENT;
-    if (size_class < 0 || size_class > 15 || (wave_w != 8 && wave_w != 16 && wave_w != 32 && wave_w != 64) ||
-        (waves_x != 1 && waves_x != 2 && waves_x != 4) || (unroll != 1 && unroll != 2 && unroll != 4))
+    const int g = lanes_per_ray;
+    const bool lanes_ok = g == 1 || g == 2 || g == 4 || g == 8 || g == 16;
+    const bool ww_ok = wave_w >= 2 && wave_w <= 64 && (wave_w & (wave_w - 1)) == 0 && lanes_ok && wave_w <= 64 / g;
+    if (size_class < 0 || size_class > 15 || !ww_ok || (waves_x != 1 && waves_x != 2 && waves_x != 4) ||
+        (unroll != 1 && unroll != 2) || (g > 1 && unroll != 1) || (min_waves != 0 && min_waves != 4) ||
+        (min_waves == 4 && (g == 2 || unroll == 2)))
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "invalid tile shape");
-    ctx->shapes[size_class] = TileShape{wave_w, waves_x, unroll};
+    ctx->shapes[size_class] = TileShape{wave_w, waves_x, unroll, g, min_waves == 4 ? 1 : 0};
     return ISAAC_OK;
 }
 
-isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_w, int* waves_x, int* unroll) {
+isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_w, int* waves_x, int* unroll,
+                                  int* lanes_per_ray, int* min_waves) {
     if (!ctx || size_class < 0 || size_class > 15) return ISAAC_ERR_INVALID_ARGUMENT;
-    if (wave_w) *wave_w = ctx->shapes[size_class].wave_w;
-    if (waves_x) *waves_x = ctx->shapes[size_class].waves_x;
-    if (unroll) *unroll = ctx->shapes[size_class].unroll;
+    const TileShape& t = ctx->shapes[size_class];
+    if (wave_w) *wave_w = t.wave_w;
+    if (waves_x) *waves_x = t.waves_x;
+    if (unroll) *unroll = t.unroll;
+    if (lanes_per_ray) *lanes_per_ray = t.lanes;
+    if (min_waves) *min_waves = t.waves_hint ? 4 : 0;
     return ISAAC_OK;
 }
 

@@ -35,6 +35,17 @@ struct DevOp {
 
 enum DType : int32_t { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 
+// Source signatures with a compile-time specialized scan-point loop (all
+// sources packed, strides below 2^23 bytes); anything else runs the generic
+// bytecode loop.  The arithmetic, and so the image, is the same either way.
+enum Signature : int32_t {
+    SIG_GENERIC = 0,
+    SIG_F32x1 = 1,        // one FP32 scalar
+    SIG_PIC3_F32 = 2,     // FP32 scalar, FP32 3-vector, FP32 3-vector
+    SIG_PIC3_F16 = 3,     // the same in FP16
+    SIG_PIC3_BF16 = 4,    // the same in BF16
+};
+
 struct DevSource {
     uint64_t base[4];      // per component: lowest byte address it can be read at
     uint32_t num_records[4];  // per component: bytes readable from base (buffer-resource range)
@@ -69,12 +80,14 @@ struct DevJob {
     int32_t n_clip;
     float ert;             // early-termination threshold
     // tile decomposition of this job's image
-    int32_t wave_w;        // rays per wave: wave_w x (64 / wave_w)
+    int32_t wave_w;        // a wave's rays form a wave_w x (64 / lanes / wave_w) block
     int32_t waves_x;       // waves per workgroup: waves_x x (4 / waves_x)
-    int32_t unroll;        // samples between early-termination checks
+    int32_t unroll;        // scan points whose loads are issued together (1 or 2)
+    int32_t lanes;         // lanes sharing one ray (1, 2, 4, 8 or 16)
+    int32_t waves_hint;    // 1: run the variant compiled for at least 4 waves per SIMD
+    int32_t sig;           // Signature of the active sources
     int32_t tiles_x, tiles_y;
     int32_t tile_begin;    // first tile index of this job in the batch
-    int32_t pad0;
     float* out;            // device RGBA32F image
     int32_t* out_samples;  // device per-pixel sample counts or null
     DevSource src[kMaxSources];
@@ -90,6 +103,9 @@ struct LaunchArgs {
     int persistent;            // 0: one workgroup per tile; 1: grid-stride over a tile queue
     int grid;                  // workgroups launched in persistent mode
     int max_src;               // widest job's active source count (sizes the LDS tables)
+    int unroll;                // scan points whose loads are issued together (kernel variant)
+    int lanes;                 // lanes per ray (kernel variant); 1 when unroll > 1
+    int waves_hint;            // 1: the variant compiled for at least 4 waves per SIMD
 };
 
 int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t

@@ -353,46 +353,308 @@ __device__ __forceinline__ float sample_source(const DevSource& S, const int dim
     return fmaf(w[2], c1 - c0, c0);
 }
 
+// Compile-time source kinds of the specialized scan-point loop.
+enum Kind : int { K_NONE = 0, K_F32x1 = 1, K_F32x3 = 2, K_F16x1 = 3, K_F16x3 = 4, K_BF16x1 = 5, K_BF16x3 = 6 };
+
+template <int K> struct KindOf { static constexpr int dim = 1, dtype = DT_F32; };
+template <> struct KindOf<K_F32x3> { static constexpr int dim = 3, dtype = DT_F32; };
+template <> struct KindOf<K_F16x1> { static constexpr int dim = 1, dtype = DT_F16; };
+template <> struct KindOf<K_F16x3> { static constexpr int dim = 3, dtype = DT_F16; };
+template <> struct KindOf<K_BF16x1> { static constexpr int dim = 1, dtype = DT_BF16; };
+template <> struct KindOf<K_BF16x3> { static constexpr int dim = 3, dtype = DT_BF16; };
+
+// Voxel offsets of one source: nearest cell, or the 8 trilinear corners with
+// the border clamp of guard-less sources.  24-bit multiplies (the host admits
+// a signature only when every stride is below 2^23 bytes).
 template <int INTERP>
-__device__ __forceinline__ void march(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R, float4& out,
-                      int& count) {
-    const float step = (float)J.step;
-    const float ert = J.ert;
-    const int n_src = J.n_src;
+__device__ __forceinline__ void corner_offsets(const DevSource& S, const int dims[3], const int (&i0)[3],
+                                               int (&off)[INTERP ? 8 : 1]) {
+    if (INTERP == 0) {
+        off[0] = __mul24(i0[0], S.stride[0]) + __mul24(i0[1], S.stride[1]) + __mul24(i0[2], S.stride[2]);
+        return;
+    }
+    int a0[3], a1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        a0[a] = i0[a];
+        a1[a] = i0[a] + 1;
+        if (S.guard < 1) {
+            a0[a] = clampi(a0[a], 0, dims[a] - 1);
+            a1[a] = clampi(a1[a], 0, dims[a] - 1);
+        }
+    }
+    const int x0 = __mul24(a0[0], S.stride[0]), x1 = __mul24(a1[0], S.stride[0]);
+    const int y0 = __mul24(a0[1], S.stride[1]), y1 = __mul24(a1[1], S.stride[1]);
+    const int z0 = __mul24(a0[2], S.stride[2]), z1 = __mul24(a1[2], S.stride[2]);
+    off[0] = x0 + y0 + z0;
+    off[1] = x1 + y0 + z0;
+    off[2] = x0 + y1 + z0;
+    off[3] = x1 + y1 + z0;
+    off[4] = x0 + y0 + z1;
+    off[5] = x1 + y0 + z1;
+    off[6] = x0 + y1 + z1;
+    off[7] = x1 + y1 + z1;
+}
+
+template <int K, int N>
+__device__ __forceinline__ void fetch_kind(const DevSource& S, const int (&off)[N], float (&v)[N][4]) {
+    constexpr int D = KindOf<K>::dim, T = KindOf<K>::dtype;
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(S.base[0], S.num_records[0]);
+    const int o = S.comp_off[0];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[i][c] = 0.f;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            if (T == DT_F32) v[i][c] = ld_f32(r, off[i] + o + 4 * c);
+            else v[i][c] = ld_scalar(r, off[i] + o + 2 * c, T);
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ float blend(const float (&c)[N], const float (&w)[3]) {
+    if (N == 1) return c[0];
+    const float c00 = fmaf(w[0], c[1] - c[0], c[0]);
+    const float c10 = fmaf(w[0], c[3] - c[2], c[2]);
+    const float c01 = fmaf(w[0], c[5] - c[4], c[4]);
+    const float c11 = fmaf(w[0], c[7] - c[6], c[6]);
+    const float c0 = fmaf(w[1], c10 - c00, c00);
+    const float c1 = fmaf(w[1], c11 - c01, c01);
+    return fmaf(w[2], c1 - c0, c0);
+}
+
+// ---------------------------------------------------------------------------
+// Scan points.  point_generic evaluates one scan point with the runtime
+// source loop (any sources); points<...> evaluates U consecutive scan points
+// for a compile-time source signature, issuing every load before any is
+// consumed (the source loop unrolled at compile time, as the paper does with
+// template metaprogramming, Sec. 3.2).  Both return the mixed premultiplied
+// colour E and opacity S of each point and share the arithmetic operation for
+// operation, so they give the same image bit for bit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mix_finish(float& S, float (&E)[3]) {
+    if (S > 1.f) {
+        const float inv = 1.f / S;
+        E[0] *= inv;
+        E[1] *= inv;
+        E[2] *= inv;
+        S = 1.f;
+    }
+}
+
+template <int INTERP>
+__device__ __forceinline__ void point_generic(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                              int k, float (&E)[3], float& S) {
+    const float tk = ((float)k + 0.5f) * (float)J.step;
+    const float p[3] = {fmaf(tk, R.d[0], R.pb[0]), fmaf(tk, R.d[1], R.pb[1]), fmaf(tk, R.d[2], R.pb[2])};
     const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
+    S = 0.f;
+    E[0] = E[1] = E[2] = 0.f;
+    for (int s = 0; s < J.n_src; ++s) {
+        const DevSource& src = J.src[s];
+        const float x = sample_source<INTERP>(src, dims, p);
+        const float4 c = classify(s_tf + s * kTfEntries, x);
+        const float wa = src.weight * c.w;
+        S += wa;
+        E[0] = fmaf(wa, c.x, E[0]);
+        E[1] = fmaf(wa, c.y, E[1]);
+        E[2] = fmaf(wa, c.z, E[2]);
+    }
+    mix_finish(S, E);
+}
+
+template <int SIG> struct SigKinds { static constexpr int k0 = K_NONE, k1 = K_NONE, k2 = K_NONE; };
+template <> struct SigKinds<SIG_F32x1> { static constexpr int k0 = K_F32x1, k1 = K_NONE, k2 = K_NONE; };
+template <> struct SigKinds<SIG_PIC3_F32> { static constexpr int k0 = K_F32x1, k1 = K_F32x3, k2 = K_F32x3; };
+template <> struct SigKinds<SIG_PIC3_F16> { static constexpr int k0 = K_F16x1, k1 = K_F16x3, k2 = K_F16x3; };
+template <> struct SigKinds<SIG_PIC3_BF16> { static constexpr int k0 = K_BF16x1, k1 = K_BF16x3, k2 = K_BF16x3; };
+
+template <int INTERP, int U, int SIG>
+__device__ __forceinline__ void points(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R, int k,
+                                       float (&E)[U][3], float (&S)[U]) {
+    if constexpr (SIG == SIG_GENERIC) {
+        static_assert(U == 1, "the generic loop evaluates one scan point at a time");
+        point_generic<INTERP>(J, s_tf, R, k, E[0], S[0]);
+    } else {
+        constexpr int K0 = SigKinds<SIG>::k0, K1 = SigKinds<SIG>::k1, K2 = SigKinds<SIG>::k2;
+        constexpr int NV = INTERP ? 8 : 1;
+        constexpr int NS = (K0 != K_NONE) + (K1 != K_NONE) + (K2 != K_NONE);
+        const float step = (float)J.step;
+        const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
+        float vals[U][3][NV][4];
+        float wts[U][3];
+        // phase 1: positions, offsets and every load of U scan points
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kk = min(k + u, R.ke - 1);
+            const float tk = ((float)kk + 0.5f) * step;
+            const float p[3] = {fmaf(tk, R.d[0], R.pb[0]), fmaf(tk, R.d[1], R.pb[1]), fmaf(tk, R.d[2], R.pb[2])};
+            int i0[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (INTERP == 0) {
+                    i0[a] = clampi((int)floorf(p[a]), 0, dims[a] - 1);
+                    wts[u][a] = 0.f;
+                } else {
+                    const float uu = p[a] - 0.5f;
+                    const float fl = floorf(uu);
+                    wts[u][a] = uu - fl;
+                    i0[a] = (int)fl;
+                }
+            }
+            int off[NV];
+            if (NS > 0) {
+                corner_offsets<INTERP>(J.src[0], dims, i0, off);
+                fetch_kind<K0, NV>(J.src[0], off, vals[u][0]);
+            }
+            if (NS > 1) {
+                corner_offsets<INTERP>(J.src[1], dims, i0, off);
+                fetch_kind<K1, NV>(J.src[1], off, vals[u][1]);
+            }
+            if (NS > 2) {
+                corner_offsets<INTERP>(J.src[2], dims, i0, off);
+                fetch_kind<K2, NV>(J.src[2], off, vals[u][2]);
+            }
+        }
+        // phase 2: functor chains, interpolation, classification and mixing
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            S[u] = 0.f;
+            E[u][0] = E[u][1] = E[u][2] = 0.f;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                float c[NV];
+                run_chain<NV>(J.src[s], vals[u][s], c);
+                const float x = blend<NV>(c, wts[u]);
+                const float4 cl = classify(s_tf + s * kTfEntries, x);
+                const float wa = J.src[s].weight * cl.w;
+                S[u] += wa;
+                E[u][0] = fmaf(wa, cl.x, E[u][0]);
+                E[u][1] = fmaf(wa, cl.y, E[u][1]);
+                E[u][2] = fmaf(wa, cl.z, E[u][2]);
+            }
+            mix_finish(S[u], E[u]);
+        }
+    }
+}
+
+// One lane per ray: classical front-to-back compositing, U scan points per
+// step, early termination at the first point whose opacity reaches ert.
+template <int INTERP, int U, int SIG>
+__device__ __forceinline__ void march_seq(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                          float4& out, int& count) {
+    const float ert = J.ert;
     float Cr = 0.f, Cg = 0.f, Cb = 0.f, A = 0.f;
     int n = 0;
-    for (int k = R.kb; k < R.ke; ++k) {
-        const float tk = ((float)k + 0.5f) * step;
-        const float p[3] = {fmaf(tk, R.d[0], R.pb[0]), fmaf(tk, R.d[1], R.pb[1]), fmaf(tk, R.d[2], R.pb[2])};
-        float S = 0.f, Er = 0.f, Eg = 0.f, Eb = 0.f;
-        for (int s = 0; s < n_src; ++s) {
-            const DevSource& src = J.src[s];
-            const float x = sample_source<INTERP>(src, dims, p);
-            const float4 c = classify(s_tf + s * kTfEntries, x);
-            const float wa = src.weight * c.w;
-            S += wa;
-            Er = fmaf(wa, c.x, Er);
-            Eg = fmaf(wa, c.y, Eg);
-            Eb = fmaf(wa, c.z, Eb);
+    bool done = false;
+    for (int k = R.kb; k < R.ke && !done; k += U) {
+        float E[U][3], S[U];
+        points<INTERP, U, SIG>(J, s_tf, R, k, E, S);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k + u < R.ke && !done) {
+                const float T = 1.f - A;
+                Cr = fmaf(T, E[u][0], Cr);
+                Cg = fmaf(T, E[u][1], Cg);
+                Cb = fmaf(T, E[u][2], Cb);
+                A = fmaf(T, S[u], A);
+                ++n;
+                if (A >= ert) done = true;
+            }
         }
-        if (S > 1.f) {
-            const float inv = 1.f / S;
-            Er *= inv;
-            Eg *= inv;
-            Eb *= inv;
-            S = 1.f;
-        }
-        const float T = 1.f - A;
-        Cr = fmaf(T, Er, Cr);
-        Cg = fmaf(T, Eg, Cg);
-        Cb = fmaf(T, Eb, Cb);
-        A = fmaf(T, S, A);
-        ++n;
-        if (A >= ert) break;
     }
     out = make_float4(Cr, Cg, Cb, A);
     count = n;
+}
+
+// Shift within rows of 16 lanes (DPP row_shr:d); lanes below d receive 0.
+template <int D>
+__device__ __forceinline__ float row_shr(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x110 + D, 0xF, 0xF,
+                                                                 true));
+}
+
+// G lanes per ray: lane g evaluates scan points kb + g, kb + g + G, ...; each
+// row of G points is composited in order with an inclusive scan of the
+// associative front-to-back operator (C, A) o (C', A') = (C + (1-A) C',
+// A + (1-A) A') across the group, then appended to the ray's running state.
+// The first point whose cumulative opacity reaches ert ends the ray, exactly
+// where the one-lane loop would stop.
+template <int INTERP, int G, int SIG>
+__device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                            int lane, float4& out, int& count) {
+    const int g = lane & (G - 1);
+    const float ert = J.ert;
+    float Cr = 0.f, Cg = 0.f, Cb = 0.f, A = 0.f;
+    int n = 0;
+    bool stop = false;
+    for (int k0 = R.kb; k0 < R.ke && !stop; k0 += G) {
+        const int k = k0 + g;
+        const bool valid = k < R.ke;
+        float E[1][3], S[1];
+        points<INTERP, 1, SIG>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
+        float c0 = valid ? E[0][0] : 0.f, c1 = valid ? E[0][1] : 0.f, c2 = valid ? E[0][2] : 0.f;
+        float a = valid ? S[0] : 0.f;
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) {
+            float o0, o1, o2, oa;
+            if (d == 1) {
+                o0 = row_shr<1>(c0); o1 = row_shr<1>(c1); o2 = row_shr<1>(c2); oa = row_shr<1>(a);
+            } else if (d == 2) {
+                o0 = row_shr<2>(c0); o1 = row_shr<2>(c1); o2 = row_shr<2>(c2); oa = row_shr<2>(a);
+            } else if (d == 4) {
+                o0 = row_shr<4>(c0); o1 = row_shr<4>(c1); o2 = row_shr<4>(c2); oa = row_shr<4>(a);
+            } else {
+                o0 = row_shr<8>(c0); o1 = row_shr<8>(c1); o2 = row_shr<8>(c2); oa = row_shr<8>(a);
+            }
+            if (g >= d) {
+                const float t = 1.f - oa;
+                c0 = fmaf(t, c0, o0);
+                c1 = fmaf(t, c1, o1);
+                c2 = fmaf(t, c2, o2);
+                a = fmaf(t, a, oa);
+            }
+        }
+        const float T = 1.f - A;
+        const float n0 = fmaf(T, c0, Cr), n1 = fmaf(T, c1, Cg), n2 = fmaf(T, c2, Cb), na = fmaf(T, a, A);
+        const unsigned long long m = __ballot(valid && na >= ert);
+        const unsigned bits = (unsigned)(m >> (lane & ~(G - 1))) & ((1u << G) - 1u);
+        int sel;
+        if (bits) {
+            sel = __builtin_ctz(bits);
+            stop = true;
+        } else {
+            sel = min(G, R.ke - k0) - 1;
+        }
+        n += sel + 1;
+        Cr = __shfl(n0, sel, G);
+        Cg = __shfl(n1, sel, G);
+        Cb = __shfl(n2, sel, G);
+        A = __shfl(na, sel, G);
+    }
+    out = make_float4(Cr, Cg, Cb, A);
+    count = n;
+}
+
+template <int INTERP, int U, int G, int SIG>
+__device__ __forceinline__ void march_sig(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                          int lane, float4& out, int& count) {
+    if constexpr (G == 1) march_seq<INTERP, (SIG == SIG_GENERIC ? 1 : U), SIG>(J, s_tf, R, out, count);
+    else march_lanes<INTERP, G, SIG>(J, s_tf, R, lane, out, count);
+}
+
+template <int INTERP, int U, int G>
+__device__ __forceinline__ void march_dispatch(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                               int lane, float4& out, int& count) {
+    switch (J.sig) {
+    case SIG_F32x1: march_sig<INTERP, U, G, SIG_F32x1>(J, s_tf, R, lane, out, count); break;
+    case SIG_PIC3_F32: march_sig<INTERP, U, G, SIG_PIC3_F32>(J, s_tf, R, lane, out, count); break;
+    case SIG_PIC3_F16: march_sig<INTERP, U, G, SIG_PIC3_F16>(J, s_tf, R, lane, out, count); break;
+    case SIG_PIC3_BF16: march_sig<INTERP, U, G, SIG_PIC3_BF16>(J, s_tf, R, lane, out, count); break;
+    default: march_sig<INTERP, U, G, SIG_GENERIC>(J, s_tf, R, lane, out, count); break;
+    }
 }
 
 __device__ __forceinline__ int find_job(const DevJob* __restrict__ jobs, int n_jobs, int tile) {
@@ -405,32 +667,28 @@ __device__ __forceinline__ int find_job(const DevJob* __restrict__ jobs, int n_j
     return lo;
 }
 
-__device__ __forceinline__ void render_tile(const DevJob& J, int t, const float4* __restrict__ s_tf) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ww = J.wave_w, wh = 64 / ww;
+// Pixel of this lane in tile t of job J (G lanes share one ray); false
+// outside the image.
+template <int G>
+__device__ __forceinline__ bool pixel_of(const DevJob& J, int t, int lane, int wave, int& px, int& py) {
+    const int ray = lane / G;
+    const int ww = J.wave_w, wh = (64 / G) / ww;
     const int gx = J.waves_x, gy = 4 / gx;
     const int tx = t % J.tiles_x, ty = t / J.tiles_x;
-    const int px = tx * (ww * gx) + (wave % gx) * ww + lane % ww;
-    const int py = ty * (wh * gy) + (wave / gx) * wh + lane / ww;
-    if (px >= J.width || py >= J.height) return;
-    RaySetup R;
-    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-    int count = 0;
-    if (setup_ray(J, px, py, R)) {
-        if (J.interp) march<1>(J, s_tf, R, c, count);
-        else march<0>(J, s_tf, R, c, count);
-    }
-    const size_t pix = (size_t)py * J.width + px;
-    reinterpret_cast<float4*>(J.out)[pix] = c;
-    if (J.out_samples) J.out_samples[pix] = count;
+    px = tx * (ww * gx) + (wave % gx) * ww + ray % ww;
+    py = ty * (wh * gy) + (wave / gx) * wh + ray / ww;
+    return px < J.width && py < J.height;
 }
 
-__global__ __launch_bounds__(kBlockThreads) void raycast_kernel(const DevJob* __restrict__ jobs,
-                                                                 const float4* __restrict__ tf_pool,
-                                                                 int* __restrict__ cursor, int n_jobs,
-                                                                 int total_tiles, int persistent) {
+// Waves-per-SIMD hint: W = 0 leaves register allocation to the compiler,
+// W > 0 asks for at least W resident waves per SIMD (fewer registers each).
+template <int U, int G, int W>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, 8)))
+void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ tf_pool, int* __restrict__ cursor,
+                    int n_jobs, int total_tiles, int persistent) {
     extern __shared__ float4 s_tf[];
     __shared__ int s_tile;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int cur_job = -1;
     for (int iter = 0;; ++iter) {
         int tile;
@@ -447,8 +705,13 @@ __global__ __launch_bounds__(kBlockThreads) void raycast_kernel(const DevJob* __
         tile = __builtin_amdgcn_readfirstlane(tile);
         const int job = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, tile));
         const DevJob& J = jobs[job];
-        if (job != cur_job) {
-            __syncthreads();
+        int px = 0, py = 0;
+        const bool in_image = pixel_of<G>(J, tile - J.tile_begin, lane, wave, px, py);
+        RaySetup R;
+        const bool hit = in_image && setup_ray(J, px, py, R);
+        // tiles no ray of which meets the box skip the transfer tables; the
+        // barrier also ends every read of the previous tile's tables
+        if (__syncthreads_or(hit) && job != cur_job) {
             const int n = J.n_src * kTfEntries;
             for (int i = threadIdx.x; i < n; i += kBlockThreads) {
                 const int s = i / kTfEntries, e = i % kTfEntries;
@@ -457,7 +720,17 @@ __global__ __launch_bounds__(kBlockThreads) void raycast_kernel(const DevJob* __
             __syncthreads();
             cur_job = job;
         }
-        render_tile(J, tile - J.tile_begin, s_tf);
+        float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+        int count = 0;
+        if (hit) {
+            if (J.interp) march_dispatch<1, U, G>(J, s_tf, R, lane, c, count);
+            else march_dispatch<0, U, G>(J, s_tf, R, lane, c, count);
+        }
+        if (in_image && (lane & (G - 1)) == 0) {
+            const size_t pix = (size_t)py * J.width + px;
+            reinterpret_cast<float4*>(J.out)[pix] = c;
+            if (J.out_samples) J.out_samples[pix] = count;
+        }
     }
 }
 
@@ -499,7 +772,15 @@ int launch_raycast(const LaunchArgs& a, void* stream) {
     const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfEntries * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(raycast_kernel, dim3(blocks), dim3(kBlockThreads), lds, (hipStream_t)stream, a.jobs,
+    auto* kernel = raycast_kernel<1, 1, 0>;
+    switch (a.lanes) {
+    case 16: kernel = a.waves_hint ? raycast_kernel<1, 16, 4> : raycast_kernel<1, 16, 0>; break;
+    case 8: kernel = a.waves_hint ? raycast_kernel<1, 8, 4> : raycast_kernel<1, 8, 0>; break;
+    case 4: kernel = a.waves_hint ? raycast_kernel<1, 4, 4> : raycast_kernel<1, 4, 0>; break;
+    case 2: kernel = raycast_kernel<1, 2, 0>; break;
+    default: kernel = a.unroll >= 2 ? raycast_kernel<2, 1, 0> : (a.waves_hint ? raycast_kernel<1, 1, 4> : raycast_kernel<1, 1, 0>);
+    }
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlockThreads), lds, (hipStream_t)stream, a.jobs,
                        reinterpret_cast<const float4*>(a.tf_pool), a.cursor, a.n_jobs, a.total_tiles, a.persistent);
     return hipGetLastError();
 }
@@ -532,7 +813,7 @@ int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, 
 }
 
 int raycast_occupancy(int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, raycast_kernel, kBlockThreads,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, raycast_kernel<1, 1, 0>, kBlockThreads,
                                                        3 * kTfEntries * sizeof(float4));
 }
 

@@ -216,17 +216,47 @@ def test_early_termination_bound(ctx):
         assert np.all(np.abs(cut.astype(np.float64) - full) <= (1.0 - theta) + 1e-5), theta
 
 
-def test_tile_shapes_give_identical_images(ctx):
+def test_tile_shapes_and_schedules(ctx):
+    """Tile shape and unroll never change a pixel; lanes-per-ray schedules agree with the oracle."""
     sc = configs.pic3(n=32, width=203, height=77)
     ref, refc = gpu_render(ctx, sc)
     cls = 8                                  # size class of a 203-wide image: ceil(log2(203))
+    rec = oracle.render(sc)
     try:
-        for ww, wx in ((16, 2), (32, 1), (64, 4), (8, 4)):
-            ctx.set_tile_shape(cls, ww, wx, 1)
+        for ww, wx, u in ((16, 2, 1), (32, 1, 1), (64, 4, 1), (8, 4, 2), (16, 1, 2)):
+            ctx.set_tile_shape(cls, ww, wx, u, 1, 0)
             img, cnt = gpu_render(ctx, sc)
-            assert np.array_equal(img, ref) and np.array_equal(cnt, refc), (ww, wx)
+            assert np.array_equal(img, ref) and np.array_equal(cnt, refc), (ww, wx, u)
+        for ww, wx, g, m in ((8, 2, 2, 0), (16, 1, 2, 0), (8, 4, 4, 0), (16, 2, 4, 4), (32, 1, 2, 0), (8, 1, 8, 0),
+                             (4, 2, 16, 4), (8, 2, 8, 4), (4, 4, 16, 0), (8, 4, 1, 4)):
+            ctx.set_tile_shape(cls, ww, wx, 1, g, m)
+            img, cnt = gpu_render(ctx, sc)
+            compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=f"lanes={g} wave_w={ww} waves_x={wx} min_waves={m}")
+            assert np.abs(img - ref).max() < 1e-5
+            again, _ = gpu_render(ctx, sc)
+            assert np.array_equal(again, img)
     finally:
-        ctx.set_tile_shape(cls, 8, 2, 1)
+        ctx.set_tile_shape(cls, 8, 2, 1, 1, 0)
+
+
+def test_lanes_per_ray_full_parity(ctx):
+    """Every feature under 2 and 4 lanes per ray (random tiny scenes) against the oracle."""
+    try:
+        for g in (2, 4, 16):
+            for c in range(16):
+                ctx.set_tile_shape(c, min(8, 64 // g), 2, 1, g, 0)
+            for seed in range(20):
+                sc = configs.random_small_scene(seed)
+                img, cnt = gpu_render(ctx, sc)
+                compare(img.reshape(-1, 4), cnt.reshape(-1), oracle.render(sc), label=f"random_small[{seed}] lanes={g}")
+                img2, cnt2 = gpu_render(ctx, sc, ert_threshold=NO_TERMINATION)
+                compare(img2.reshape(-1, 4), cnt2.reshape(-1), oracle.render(sc, ert_threshold=NO_TERMINATION),
+                        label=f"random_small[{seed}] lanes={g} no-termination")
+            sc = configs.pic3(n=48, width=300, height=170)
+            full_parity(ctx, sc, f"pic3 48^3 lanes={g}")
+    finally:
+        for c in range(16):
+            ctx.set_tile_shape(c, 8, 2, 1, 1, 0)
 
 
 def test_tiny_and_ragged_images(ctx):
