@@ -2,14 +2,19 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload: density (lognormal background x cylindrical wake), E and B
-(divergence-free sinusoids; chains `length` and `length | mul(2) | pow(0.5)`)
+Headline workload: density (lognormal background x cylindrical wake), E and
+B (divergence-free sinusoids; chains `length` and `length | mul(2) | pow(0.5)`)
 on a 256^3 grid with one guard layer and 256-byte row pitch, trilinear
 sampling, step 0.5 voxel, two clipping planes, 8-point transfer functions,
 weights in [0.3,1], rendered at 1920x1080 from the 26 neighbour directions of
 a cube cell at twice the grid diagonal (fovy 60).  One step = one frame (one
 view; steps cycle through the 26 views).  Sources are resident in device
-memory before timing starts.
+memory before timing starts; `value` counts the scan points composited
+(counted once per view by the kernel's counting variant, untimed).
+
+Also reported (not the headline): the same scene with FP16 and BF16 storage,
+the 64-sub-volume batch in one persistent hipGraph launch, and a short run of
+the continuous-batching server on a resident 512x512x256 volume.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -20,6 +25,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -29,6 +35,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ray samples/sec (Gsamples/s) + frames/s at 1920x1080; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+TUNED = os.path.join(ROOT, "paper_1611_09048_amd", "tuned_gfx950.json")
+# candidates the bench tunes over when its cache has no entry
+QUICK = dict(lanes=(4, 8, 16), wave_ws=(4, 8, 16), waves_xs=(1, 2, 4), unrolls=(1,), min_waves=(0, 4))
 
 
 def log(*a):
@@ -40,8 +49,6 @@ def cpu_baseline(scene, gpu_counts, row_stride: int, threads: int):
     import oracle
     rows = np.arange(0, scene.height, row_stride)
     px = np.stack(np.meshgrid(np.arange(scene.width), rows), axis=-1).reshape(-1, 2).astype(np.int32)
-    # split the pixel list over threads running the single-threaded oracle
-    import threading
     parts = np.array_split(np.arange(px.shape[0]), threads)
     outs = [None] * threads
 
@@ -65,6 +72,168 @@ def cpu_baseline(scene, gpu_counts, row_stride: int, threads: int):
                        f"on {agree * 100:.2f}% of them")
 
 
+def apply_tuning(ctx, key_sig, classes, time_jobs, retune=False):
+    """Set the tile shape of `classes` from the cache, tuning (one shape for all) when missing."""
+    from paper_1611_09048_amd import autotune
+    cache = autotune.load_cache(TUNED)
+    key = autotune.cache_key("gfx950", "+".join(map(str, classes)), key_sig)
+    if key in cache and not retune:
+        best = tuple(cache[key])
+    else:
+        times = {}
+        for cand in autotune.candidates(**QUICK):
+            for c in classes:
+                ctx.set_tile_shape(c, *cand)
+            times[cand] = time_jobs()
+        best = autotune.pick(times)
+        log(f"bench: tuned {key}: {best} {times[best]:.4f} ms (of {len(times)} candidates)")
+        cache[key] = list(best)
+        try:
+            autotune.save_cache(TUNED, cache)
+        except OSError:
+            pass
+    for c in classes:
+        ctx.set_tile_shape(c, *best)
+    return best
+
+
+def frames(ctx, sc, steps, warmup, log_prefix=""):
+    """Time `steps` frames cycling through the 26 views; returns a dict of results."""
+    import torch
+    from paper_1611_09048_amd import ASYNC, TIMING, device
+    from scenes import configs
+    stream = torch.cuda.current_stream()
+    vol = device.upload_volume(ctx, sc, 0)
+    img = device.new_image(sc)
+    cnt = device.new_counts(sc)
+    views = configs.views26()
+    scenes_v = [sc.with_(camera=configs.orbit_camera(sc.dims, v)) for v in views]
+    jobs = [device.render_job(s, 0, img) for s in scenes_v]
+
+    def time_jobs():
+        ctx.render([jobs[0]])
+        ctx.timing()
+        for j in (jobs[0], jobs[8], jobs[13], jobs[20]):
+            ctx.render([j], TIMING)
+        ms, n = ctx.timing()
+        return ms / n
+
+    from paper_1611_09048_amd import autotune
+    sig = f"pic3:{sc.sources[0].dtype}"
+    shape = apply_tuning(ctx, sig, [autotune.size_class(sc.width, sc.height)], time_jobs)
+    samples, hit = [], []
+    for s in scenes_v:
+        ctx.render([device.render_job(s, 0, img, cnt)])
+        c = cnt.to(torch.int64)
+        samples.append(int(c.sum().item()))
+        hit.append(float((c > 0).float().mean().item()))
+    ctx.render([device.render_job(scenes_v[0], 0, img, cnt)])
+    counts_view0 = cnt.cpu().numpy()
+    log(f"bench:{log_prefix} samples/frame mean {np.mean(samples):.4g} (min {min(samples)}, max {max(samples)}); "
+        f"hit fraction {np.mean(hit):.3f}; tile shape {shape}")
+    for k in range(warmup):
+        ctx.render([jobs[k % len(jobs)]], ASYNC)
+    torch.cuda.synchronize()
+    ctx.timing()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        ctx.render([jobs[k % len(jobs)]], ASYNC | TIMING)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms, n_kernels = ctx.timing()
+    frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    total = sum(samples[k % len(jobs)] for k in range(steps))
+    per_view = np.zeros(len(views))
+    reps = np.zeros(len(views))
+    for k in range(steps):
+        per_view[k % len(jobs)] += frame_ms[k]
+        reps[k % len(jobs)] += 1
+    per_view = per_view[reps > 0] / reps[reps > 0]
+    out = dict(gsps=total / elapsed / 1e9, elapsed=elapsed, kernel_ms=kernel_ms / max(n_kernels, 1),
+               frame_ms=frame_ms, per_view=per_view, samples=samples, shape=shape, counts_view0=counts_view0,
+               scene_v0=scenes_v[0], field_bytes=sum(s.field_bytes() for s in sc.sources),
+               image_bytes=sc.width * sc.height * 16)
+    log(f"bench:{log_prefix} {steps} frames in {elapsed * 1e3:.1f} ms -> {out['gsps']:.2f} Gsamples/s; "
+        f"kernel avg {out['kernel_ms']:.4f} ms")
+    del vol
+    return out
+
+
+def batch64(ctx, steps):
+    """The 64-sub-volume workload as one batched launch (hipGraph replay)."""
+    import torch
+    from paper_1611_09048_amd import ASYNC, TIMING, autotune, device
+    from scenes import configs
+    scs = configs.batch64()
+    vols = [device.upload_volume(ctx, sc, vid) for vid, sc in enumerate(scs)]
+    imgs = [device.new_image(sc) for sc in scs]
+    cnts = [device.new_counts(sc) for sc in scs]
+    jobs = [device.render_job(sc, vid, imgs[vid]) for vid, sc in enumerate(scs)]
+    classes = sorted({autotune.size_class(sc.width, sc.height) for sc in scs})
+
+    def time_jobs():
+        ctx.render(jobs)
+        ctx.timing()
+        for _ in range(2):
+            ctx.render(jobs, TIMING)
+        ms, n = ctx.timing()
+        return ms / n
+
+    shape = apply_tuning(ctx, "batch64:f32x1", classes, time_jobs)
+    ctx.render([device.render_job(sc, vid, imgs[vid], cnts[vid]) for vid, sc in enumerate(scs)])
+    samples = int(sum(int(c.to(torch.int64).sum().item()) for c in cnts))
+    ctx.render(jobs, ASYNC)
+    torch.cuda.synchronize()
+    ctx.timing()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.render(jobs, ASYNC | TIMING)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, n = ctx.timing()
+    res = dict(jobs=len(scs), samples_per_batch=samples, launch_ms=round(el * 1e3 / steps, 4),
+               graph_ms=round(ms / max(n, 1), 4), gsamples_per_s=round(samples * steps / el / 1e9, 3),
+               jobs_per_s=round(len(scs) * steps / el, 1), tile_shape=list(shape),
+               rays=int(sum(sc.width * sc.height for sc in scs)))
+    log(f"bench: batch64 {res}")
+    del vols
+    return res
+
+
+def serving(ctx, duration: float, rate: float, n: int = 512, depth: int = 256):
+    """Continuous-batching server on a resident n x n x depth three-source volume."""
+    from paper_1611_09048_amd import device, serve
+    from scenes import configs
+    dims = (n, n, depth)
+    vol_scene = configs.pic3(dims=dims, width=16, height=16)
+    vol = device.upload_volume(ctx, vol_scene, 200)
+    ex = serve.DeviceExecutor(ctx, vol, dims)
+    srv = serve.Server(ex, time.perf_counter, max_batch=16, max_batches_in_flight=3)
+    reqs = configs.serving_requests(11, dims, n_clients=4, rate_per_client=rate / 4, duration=duration,
+                                    base_tfs=[s.tf for s in vol_scene.sources])
+    dur = serve.run(srv, reqs, time.perf_counter, make_job=serve.job_from_request)
+    out = srv.summary(dur)
+    out.update(volume=list(dims), offered_rate=rate, requests=len(reqs))
+    log(f"bench: serving {out}")
+    del vol
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+
+
+def copy_probe(ctx_unused, mib: int = 512, reps: int = 3):
+    """A plain device copy of known size, for normalizing rocprof byte counters."""
+    import torch
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    return dict(bytes_read=x.numel() * 4, bytes_written=y.numel() * 4, kernels=reps)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,102 +243,65 @@ def main():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--views", type=int, default=26)
     ap.add_argument("--cpu-row-stride", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the ray caster has no multi-GPU path "
-              f"in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): every job of this ray caster is "
+              f"rendered by one GPU and there is no multi-GPU path in this build", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_1611_09048_amd import ASYNC, TIMING, Context, device
+    from paper_1611_09048_amd import Context
     from scenes import configs
 
     torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = Context(device=0, stream=stream, mem_budget=4 << 30)
+    if args.copy_probe:
+        log("bench: copy probe", copy_probe(ctx))
     log(f"bench: generating pic3 {args.n}^3 {args.dtype} {args.width}x{args.height}")
     sc = configs.pic3(n=args.n, width=args.width, height=args.height, dtype=args.dtype)
-    stream = torch.cuda.current_stream()
-    ctx = Context(device=0, stream=stream)
-    vol = device.upload_volume(ctx, sc, 0)
-    img = device.new_image(sc)
-    cnt = device.new_counts(sc)
-    views = configs.views26()[: args.views]
-    scenes_v = [sc.with_(camera=configs.orbit_camera(sc.dims, v)) for v in views]
-    jobs = [device.render_job(s, 0, img) for s in scenes_v]
-    log("bench: counting samples per view (untimed)")
-    samples = []
-    hit = []
-    for s in scenes_v:
-        ctx.render([device.render_job(s, 0, img, cnt)])
-        c = cnt.to(torch.int64)
-        samples.append(int(c.sum().item()))
-        hit.append(float((c > 0).float().mean().item()))
-    counts_view0 = None
-    ctx.render([device.render_job(scenes_v[0], 0, img, cnt)])
-    counts_view0 = cnt.cpu().numpy()
-    log(f"bench: samples/frame mean {np.mean(samples):.4g} (min {min(samples)}, max {max(samples)}); "
-        f"hit fraction {np.mean(hit):.3f}")
-
-    for k in range(args.warmup):
-        ctx.render([jobs[k % len(jobs)]], ASYNC)
-    torch.cuda.synchronize()
-    ctx.timing()    # discard warm-up timings
-
-    # timed region: K frames cycling through the views
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        ctx.render([jobs[k % len(jobs)]], ASYNC | TIMING)
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    kernel_ms, n_kernels = ctx.timing()
-    frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    total_samples = sum(samples[k % len(jobs)] for k in range(args.steps))
-    gsps = total_samples / elapsed / 1e9
-    per_view = np.zeros(len(views))
-    for k in range(args.steps):
-        per_view[k % len(jobs)] += frame_ms[k]
-    reps = np.bincount(np.arange(args.steps) % len(jobs), minlength=len(jobs))
-    per_view = per_view / np.maximum(reps, 1)
-    log(f"bench: {args.steps} frames in {elapsed * 1e3:.1f} ms -> {gsps:.2f} Gsamples/s; kernel avg "
-        f"{kernel_ms / max(n_kernels, 1):.3f} ms")
-
-    # roofline of the ray-casting kernel: every source byte once plus the image, per launch
-    field_bytes = sum(s.field_bytes() for s in sc.sources)
-    image_bytes = sc.width * sc.height * 16
-    algo_bytes = field_bytes + image_bytes
-    kavg_s = kernel_ms / max(n_kernels, 1) / 1e3
-    achieved = algo_bytes / kavg_s / 1e9
+    fr = frames(ctx, sc, args.steps, args.warmup)
+    algo_bytes = fr["field_bytes"] + fr["image_bytes"]
+    achieved = algo_bytes / (fr["kernel_ms"] / 1e3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel="raycast_kernel", kernel_avg_ms=round(kavg_s * 1e3, 4),
-                    algorithmic_bytes_per_launch=algo_bytes)
-
-    out = dict(metric=METRIC, value=round(gsps, 3), unit="Gsamples/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=round(elapsed * 1e3 / args.steps, 4), higher_is_better=True,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel="raycast_kernel",
+                    kernel_avg_ms=round(fr["kernel_ms"], 4), algorithmic_bytes_per_launch=algo_bytes)
+    out = dict(metric=METRIC, value=round(fr["gsps"], 3), unit="Gsamples/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(fr["elapsed"] * 1e3 / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype=args.dtype, data="synthetic",
                config=dict(workload=f"pic3: density+E+B {args.n}^3, 1 guard layer, trilinear, step 0.5, "
-                                    f"2 clip planes, {args.width}x{args.height}, {len(views)} views",
-                           grid=args.n, width=args.width, height=args.height, sources=3,
-                           storage=args.dtype, views=len(views)),
-               fps=round(args.steps / elapsed, 2),
-               latency_ms=dict(p50=round(float(np.percentile(frame_ms, 50)), 4),
-                               p99=round(float(np.percentile(frame_ms, 99)), 4)),
-               views_ms=dict(avg=round(float(per_view.mean()), 4), min=round(float(per_view.min()), 4),
-                             max=round(float(per_view.max()), 4)),
-               samples_per_frame=int(np.mean(samples)),
+                                    f"2 clip planes, {args.width}x{args.height}, 26 views",
+                           grid=args.n, width=args.width, height=args.height, sources=3, storage=args.dtype,
+                           views=26, tile_shape=list(fr["shape"])),
+               fps=round(args.steps / fr["elapsed"], 2),
+               latency_ms=dict(p50=round(float(np.percentile(fr["frame_ms"], 50)), 4),
+                               p99=round(float(np.percentile(fr["frame_ms"], 99)), 4)),
+               views_ms=dict(avg=round(float(fr["per_view"].mean()), 4), min=round(float(fr["per_view"].min()), 4),
+                             max=round(float(fr["per_view"].max()), 4)),
+               samples_per_frame=int(np.mean(fr["samples"])),
                roofline=roofline)
+    if not args.no_extras:
+        extras = {}
+        for dt in ("f16", "bf16"):
+            if dt == args.dtype:
+                continue
+            s2 = configs.pic3(n=args.n, width=args.width, height=args.height, dtype=dt)
+            f2 = frames(ctx, s2, max(26, args.steps // 2), 3, f" {dt}")
+            extras[dt] = dict(gsamples_per_s=round(f2["gsps"], 3), kernel_ms=round(f2["kernel_ms"], 4),
+                              fps=round(max(26, args.steps // 2) / f2["elapsed"], 2), tile_shape=list(f2["shape"]))
+        extras["batch64"] = batch64(ctx, 10)
+        extras["serving"] = serving(ctx, args.serve_seconds, 200.0)
+        extras["serving_stress"] = serving(ctx, max(2.0, args.serve_seconds / 2), 2000.0)
+        out["extras"] = extras
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
         log(f"bench: CPU oracle baseline on {threads} threads")
-        out["cpu_baseline"] = cpu_baseline(scenes_v[0], counts_view0, args.cpu_row_stride, threads)
-    del vol
+        out["cpu_baseline"] = cpu_baseline(fr["scene_v0"], fr["counts_view0"], args.cpu_row_stride, threads)
     ctx.close()
     print(json.dumps(out), flush=True)
 

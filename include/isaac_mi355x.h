@@ -186,7 +186,8 @@ isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count);
  *     are issued together;
  *   min_waves in {0,4}: 4 selects the kernel variant compiled to keep at
  *     least 4 waves resident per SIMD (not with lanes_per_ray 2 or unroll 2).
- * Jobs batched into one launch share its lanes_per_ray, unroll and min_waves.
+ * A batch runs one launch per distinct schedule, so each job is rendered as
+ * it would be alone.
  * Defaults: (8, 2, 1, 1, 0).  Settings with one lane per ray give the same
  * image bit for bit; more lanes composite each row of scan points by a scan,
  * which changes only FP32 rounding; a given setting always reproduces its
@@ -211,6 +212,10 @@ isaac_status isaac_submit_batch(isaac_context* ctx, const isaac_render_desc* job
 /* *done = 1 once the image is complete; *out_rgba then points at it (device,
  * owned by the library until isaac_release). */
 isaac_status isaac_poll(isaac_context* ctx, uint64_t ticket, int* done, const float** out_rgba);
+
+/* Copy a ticket's image (waiting for it) into host memory of height*width*4
+ * floats. */
+isaac_status isaac_read_image(isaac_context* ctx, uint64_t ticket, float* host_rgba);
 
 /* Return the image memory of a completed (or not yet complete: waits) ticket. */
 isaac_status isaac_release(isaac_context* ctx, uint64_t ticket);

@@ -69,7 +69,7 @@ class RenderDesc(ctypes.Structure):
 EXPORTS = ["isaac_init", "isaac_destroy", "isaac_last_error", "isaac_init_error", "isaac_set_sources",
            "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_timing",
            "isaac_set_tile_shape", "isaac_get_tile_shape", "isaac_submit", "isaac_submit_batch", "isaac_poll",
-           "isaac_release", "isaac_serving_usage", "isaac_check_functor_chain", "isaac_version"]
+           "isaac_release", "isaac_read_image", "isaac_serving_usage", "isaac_check_functor_chain", "isaac_version"]
 
 _lib = None
 
@@ -106,6 +106,7 @@ def load(path: Optional[str] = None):
                                        ctypes.POINTER(ctypes.c_uint64)]
     lib.isaac_poll.argtypes = [c_ctx, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_void_p)]
     lib.isaac_release.argtypes = [c_ctx, ctypes.c_uint64]
+    lib.isaac_read_image.argtypes = [c_ctx, ctypes.c_uint64, ctypes.c_void_p]
     lib.isaac_serving_usage.argtypes = [c_ctx, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                         ctypes.POINTER(ctypes.c_int)]
     lib.isaac_check_functor_chain.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -231,6 +232,11 @@ class Context:
 
     def release(self, ticket: int):
         self._check(self.lib.isaac_release(self.h, ctypes.c_uint64(ticket)))
+
+    def read_image(self, ticket: int, out):
+        """Copy a ticket's image into the float32 numpy array `out` (height, width, 4)."""
+        self._check(self.lib.isaac_read_image(self.h, ctypes.c_uint64(ticket), out.ctypes.data))
+        return out
 
     def serving_usage(self):
         u, b, n = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()

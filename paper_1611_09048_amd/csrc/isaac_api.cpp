@@ -228,7 +228,7 @@ struct RingSlot {
     // graph cache
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    int g_jobs = -1, g_tiles = -1, g_grid = -1, g_src = -1, g_unroll = -1, g_lanes = -1, g_hint = -1;
+    int g_jobs = -1, g_tiles = -1, g_grid = -1, g_src = -1, g_unroll = -1, g_lanes = -1, g_hint = -1, g_sig = -2;
 };
 
 struct Pending {
@@ -685,6 +685,10 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     la.unroll = unroll;
     la.lanes = lanes;
     la.waves_hint = (lanes == 2 || unroll > 1) ? 0 : hint;
+    la.sig = djs[0].sig;
+    for (const DevJob& dj : djs)
+        if (dj.sig != la.sig) la.sig = -1;
+    if (la.sig == SIG_GENERIC) la.sig = -1;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (flags & ISAAC_TIMING) {
         t0 = get_event(ctx);
@@ -694,7 +698,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     const bool use_graph = n > 1 && !(flags & ISAAC_NO_GRAPH);
     if (use_graph) {
         if (!r->exec || r->g_jobs != n || r->g_tiles != tiles || r->g_grid != la.grid || r->g_src != la.max_src ||
-            r->g_unroll != la.unroll || r->g_lanes != la.lanes || r->g_hint != la.waves_hint) {
+            r->g_unroll != la.unroll || r->g_lanes != la.lanes || r->g_hint != la.waves_hint || r->g_sig != la.sig) {
             if (r->exec) hipGraphExecDestroy(r->exec);
             if (r->graph) hipGraphDestroy(r->graph);
             r->exec = nullptr;
@@ -719,6 +723,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
             r->g_unroll = la.unroll;
             r->g_lanes = la.lanes;
             r->g_hint = la.waves_hint;
+            r->g_sig = la.sig;
         }
         if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
         HIP_TRY(ctx, hipGraphLaunch(r->exec, stream));
@@ -783,8 +788,27 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
             ++k;
         }
     }
-    st = enqueue_jobs(ctx, jobs, djs, max_src, flags, stream);
-    if (st) return st;
+    // one launch per scan-point schedule, so every job is rendered exactly as
+    // it would be alone (its size class's lanes per ray, unroll and variant)
+    std::vector<std::vector<DevJob>> groups;
+    std::vector<int> keys;
+    for (const DevJob& dj : djs) {
+        const int key = dj.lanes * 16 + dj.unroll * 2 + dj.waves_hint;
+        size_t g = 0;
+        while (g < keys.size() && keys[g] != key) ++g;
+        if (g == keys.size()) {
+            keys.push_back(key);
+            groups.emplace_back();
+        }
+        groups[g].push_back(dj);
+    }
+    for (const auto& grp : groups) {
+        int ms = 1;
+        for (const DevJob& dj : grp) ms = std::max(ms, (int)dj.n_src);
+        st = enqueue_jobs(ctx, jobs, grp, ms, flags, stream);
+        if (st) return st;
+    }
+    (void)max_src;
     if (!(flags & ISAAC_ASYNC)) {
         HIP_TRY(ctx, hipStreamSynchronize(stream));
         update_completed(ctx);
@@ -1203,6 +1227,19 @@ isaac_status isaac_release(isaac_context* ctx, uint64_t ticket) {
     ctx->cached += t.bytes;
     ctx->tickets.erase(it);
     update_completed(ctx);
+    return ISAAC_OK;
+}
+
+isaac_status isaac_read_image(isaac_context* ctx, uint64_t ticket, float* host_rgba) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) return set_err(ctx, ISAAC_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!host_rgba) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "host_rgba is NULL");
+    Ticket& t = it->second;
+    HIP_TRY(ctx, hipEventSynchronize(t.ev));
+    t.done = true;
+    HIP_TRY(ctx, hipMemcpy(host_rgba, t.out, t.bytes, hipMemcpyDeviceToHost));
     return ISAAC_OK;
 }
 

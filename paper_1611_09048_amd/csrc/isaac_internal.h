@@ -106,6 +106,7 @@ struct LaunchArgs {
     int unroll;                // scan points whose loads are issued together (kernel variant)
     int lanes;                 // lanes per ray (kernel variant); 1 when unroll > 1
     int waves_hint;            // 1: the variant compiled for at least 4 waves per SIMD
+    int sig;                   // the jobs' common Signature, or -1 when they differ
 };
 
 int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t

@@ -121,9 +121,11 @@ __device__ __forceinline__ float pow_f32(float x, float y) {
 }
 
 // Functor chain over N dates at once: one wave-uniform dispatch per functor,
-// N dates of work inside.  res[i] is component 0 of date i's result.
-template <int N>
-__device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], float (&res)[N]) {
+// N dates of work inside.  D bounds the feature dimension at compile time
+// (components D..3 are never touched); res[i] is component 0 of date i's
+// result.
+template <int N, int D = 4>
+__device__ __forceinline__ void run_chain_n(const DevSource& S, float (&v)[N][4], float (&res)[N]) {
     const int n_ops = S.n_ops;
     for (int o = 0; o < n_ops; ++o) {
         const DevOp& op = S.ops[o];
@@ -132,28 +134,28 @@ __device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], 
         switch (op.kind) {
         case OP_ADD:
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < D; ++c)
                 if (c < dim)
 #pragma unroll
                     for (int i = 0; i < N; ++i) v[i][c] = v[i][c] + a[c];
             break;
         case OP_MUL:
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < D; ++c)
                 if (c < dim)
 #pragma unroll
                     for (int i = 0; i < N; ++i) v[i][c] = v[i][c] * a[c];
             break;
         case OP_POW:
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < D; ++c)
                 if (c < dim)
 #pragma unroll
                     for (int i = 0; i < N; ++i) v[i][c] = pow_f32(v[i][c], a[c]);
             break;
         case OP_SQRT:
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < D; ++c)
                 if (c < dim)
 #pragma unroll
                     for (int i = 0; i < N; ++i)
@@ -161,34 +163,28 @@ __device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], 
             break;
         case OP_SQUARE:
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < D; ++c)
                 if (c < dim)
 #pragma unroll
                     for (int i = 0; i < N; ++i) v[i][c] = v[i][c] * v[i][c];
             break;
         case OP_LENGTH:
-            if (dim == 3) {
 #pragma unroll
-                for (int i = 0; i < N; ++i)
-                    v[i][0] = __builtin_amdgcn_sqrtf(fmaf(v[i][2], v[i][2], fmaf(v[i][1], v[i][1], v[i][0] * v[i][0])));
-            } else {
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    float s = v[i][0] * v[i][0];
-                    if (dim > 1) s = fmaf(v[i][1], v[i][1], s);
-                    if (dim > 2) s = fmaf(v[i][2], v[i][2], s);
-                    if (dim > 3) s = fmaf(v[i][3], v[i][3], s);
-                    v[i][0] = __builtin_amdgcn_sqrtf(s);
-                }
+            for (int i = 0; i < N; ++i) {
+                float s = v[i][0] * v[i][0];
+                if (D > 1 && dim > 1) s = fmaf(v[i][1], v[i][1], s);
+                if (D > 2 && dim > 2) s = fmaf(v[i][2], v[i][2], s);
+                if (D > 3 && dim > 3) s = fmaf(v[i][3], v[i][3], s);
+                v[i][0] = __builtin_amdgcn_sqrtf(s);
             }
             break;
         case OP_SUM:
 #pragma unroll
             for (int i = 0; i < N; ++i) {
                 float s = v[i][0];
-                if (dim > 1) s = s + v[i][1];
-                if (dim > 2) s = s + v[i][2];
-                if (dim > 3) s = s + v[i][3];
+                if (D > 1 && dim > 1) s = s + v[i][1];
+                if (D > 2 && dim > 2) s = s + v[i][2];
+                if (D > 3 && dim > 3) s = s + v[i][3];
                 v[i][0] = s;
             }
             break;
@@ -198,6 +194,31 @@ __device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], 
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) res[i] = v[i][0];
+}
+
+// The 8 trilinear corners run the bytecode in two groups of 4, which bounds
+// the interpreter's live registers (more resident waves).
+template <int N, int D = 4>
+__device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], float (&res)[N]) {
+    if constexpr (N == 8) {
+        float a[4][4], b[4][4], ra[4], rb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                a[i][c] = v[i][c];
+                b[i][c] = v[i + 4][c];
+            }
+        run_chain_n<4, D>(S, a, ra);
+        run_chain_n<4, D>(S, b, rb);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            res[i] = ra[i];
+            res[i + 4] = rb[i];
+        }
+    } else {
+        run_chain_n<N, D>(S, v, res);
+    }
 }
 
 // Transfer-table lookup: clamp to [0,1] (NaN -> 0), 255 intervals, linear.
@@ -259,44 +280,23 @@ __device__ __forceinline__ bool setup_ray(const DevJob& J, int px, int py, RaySe
     if (lo < 0.0) lo = 0.0;
     if (!(hi > lo)) return false;
     const double t0 = lo, t1 = hi, step = J.step;
-    // number of k >= 0 with t0 + (k + 1/2) step < t1
-    double r = (t1 - t0) / step - 0.5;
-    int n = r > 0.0 ? (int)fmin(ceil(r), 2147483000.0) : 0;
-    while (n > 0 && !(t0 + ((double)(n - 1) + 0.5) * step < t1)) --n;
-    while (t0 + ((double)n + 0.5) * step < t1) ++n;
-    int kb = 0, ke = n;
-    // each plane keeps one interval of k; evaluate the plane at p(k) exactly
-    // as written (o + t d, then n.p + d) at the interval ends
-    for (int c = 0; c < J.n_clip && kb < ke; ++c) {
+    // scan points t_k = t0 + (k + 1/2) step with t_k < t1: k < (t1 - t0)/step - 1/2
+    const double r = (t1 - t0) / step - 0.5;
+    int kb = 0, ke = r > 0.0 ? (int)ceil(fmin(r, 2.0e9)) : 0;
+    // each plane keeps one interval of k: n.(o + t d) + d >= 0 is affine in t.
+    // Bounds in closed form; a point this can misplace lies within FP64
+    // rounding of the plane, far inside the decision margin
+    for (int c = 0; c < J.n_clip; ++c) {
         const double* pl = J.clip[c];
         const double nd = pl[0] * d[0] + pl[1] * d[1] + pl[2] * d[2];
-        auto keep = [&](int k) {
-#pragma clang fp contract(off)
-            const double t = t0 + ((double)k + 0.5) * step;
-            const double p0 = o[0] + t * d[0], p1 = o[1] + t * d[1], p2 = o[2] + t * d[2];
-            return pl[0] * p0 + pl[1] * p1 + pl[2] * p2 + pl[3] >= 0.0;
-        };
         const double no = pl[0] * o[0] + pl[1] * o[1] + pl[2] * o[2] + pl[3];
         if (nd == 0.0) {
-            if (!keep(kb)) ke = kb;
+            if (no < 0.0) ke = kb;
             continue;
         }
-        // crossing parameter and the sample index near it
-        const double tc = -no / nd;
-        double kc = (tc - t0) / step - 0.5;
-        kc = fmin(fmax(kc, (double)kb - 1.0), (double)ke + 1.0);
-        int k = (int)ceil(kc);
-        if (nd > 0.0) {     // kept for k >= first kept index
-            k = clampi(k, kb, ke);
-            while (k > kb && keep(k - 1)) --k;
-            while (k < ke && !keep(k)) ++k;
-            kb = k;
-        } else {            // kept for k < first dropped index
-            k = clampi(k, kb, ke);
-            while (k < ke && keep(k)) ++k;
-            while (k > kb && !keep(k - 1)) --k;
-            ke = k;
-        }
+        const double kc = fmin(fmax((-no / nd - t0) / step - 0.5, -1.0), 2.0e9);
+        if (nd > 0.0) kb = max(kb, (int)ceil(kc));          // kept for k >= kc
+        else ke = min(ke, (int)floor(kc) + 1);              // kept for k <= kc
     }
     if (kb >= ke) return false;
     for (int a = 0; a < 3; ++a) {
@@ -471,7 +471,10 @@ template <> struct SigKinds<SIG_PIC3_F32> { static constexpr int k0 = K_F32x1, k
 template <> struct SigKinds<SIG_PIC3_F16> { static constexpr int k0 = K_F16x1, k1 = K_F16x3, k2 = K_F16x3; };
 template <> struct SigKinds<SIG_PIC3_BF16> { static constexpr int k0 = K_BF16x1, k1 = K_BF16x3, k2 = K_BF16x3; };
 
-template <int INTERP, int U, int SIG>
+// PS (per source): load, chain, blend and classify one source before the
+// next one's loads; fewer live registers (more resident waves) at the cost of
+// one memory round trip per source.  Same arithmetic either way.
+template <int INTERP, int U, int SIG, bool PS>
 __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R, int k,
                                        float (&E)[U][3], float (&S)[U]) {
     if constexpr (SIG == SIG_GENERIC) {
@@ -479,70 +482,97 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
         point_generic<INTERP>(J, s_tf, R, k, E[0], S[0]);
     } else {
         constexpr int K0 = SigKinds<SIG>::k0, K1 = SigKinds<SIG>::k1, K2 = SigKinds<SIG>::k2;
+        constexpr int KS[3] = {K0, K1, K2};
         constexpr int NV = INTERP ? 8 : 1;
         constexpr int NS = (K0 != K_NONE) + (K1 != K_NONE) + (K2 != K_NONE);
         const float step = (float)J.step;
         const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
-        float vals[U][3][NV][4];
+        int i0[U][3];
         float wts[U][3];
-        // phase 1: positions, offsets and every load of U scan points
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = min(k + u, R.ke - 1);
             const float tk = ((float)kk + 0.5f) * step;
             const float p[3] = {fmaf(tk, R.d[0], R.pb[0]), fmaf(tk, R.d[1], R.pb[1]), fmaf(tk, R.d[2], R.pb[2])};
-            int i0[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (INTERP == 0) {
-                    i0[a] = clampi((int)floorf(p[a]), 0, dims[a] - 1);
+                    i0[u][a] = clampi((int)floorf(p[a]), 0, dims[a] - 1);
                     wts[u][a] = 0.f;
                 } else {
                     const float uu = p[a] - 0.5f;
                     const float fl = floorf(uu);
                     wts[u][a] = uu - fl;
-                    i0[a] = (int)fl;
+                    i0[u][a] = (int)fl;
                 }
             }
-            int off[NV];
-            if (NS > 0) {
-                corner_offsets<INTERP>(J.src[0], dims, i0, off);
-                fetch_kind<K0, NV>(J.src[0], off, vals[u][0]);
-            }
-            if (NS > 1) {
-                corner_offsets<INTERP>(J.src[1], dims, i0, off);
-                fetch_kind<K1, NV>(J.src[1], off, vals[u][1]);
-            }
-            if (NS > 2) {
-                corner_offsets<INTERP>(J.src[2], dims, i0, off);
-                fetch_kind<K2, NV>(J.src[2], off, vals[u][2]);
-            }
-        }
-        // phase 2: functor chains, interpolation, classification and mixing
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
             S[u] = 0.f;
             E[u][0] = E[u][1] = E[u][2] = 0.f;
+        }
+        auto accumulate = [&](int u, int s, float x) {
+            const float4 cl = classify(s_tf + s * kTfEntries, x);
+            const float wa = J.src[s].weight * cl.w;
+            S[u] += wa;
+            E[u][0] = fmaf(wa, cl.x, E[u][0]);
+            E[u][1] = fmaf(wa, cl.y, E[u][1]);
+            E[u][2] = fmaf(wa, cl.z, E[u][2]);
+        };
+        if constexpr (PS) {
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                float c[NV];
-                run_chain<NV>(J.src[s], vals[u][s], c);
-                const float x = blend<NV>(c, wts[u]);
-                const float4 cl = classify(s_tf + s * kTfEntries, x);
-                const float wa = J.src[s].weight * cl.w;
-                S[u] += wa;
-                E[u][0] = fmaf(wa, cl.x, E[u][0]);
-                E[u][1] = fmaf(wa, cl.y, E[u][1]);
-                E[u][2] = fmaf(wa, cl.z, E[u][2]);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    int off[NV];
+                    float v[NV][4], c[NV];
+                    corner_offsets<INTERP>(J.src[s], dims, i0[u], off);
+                    if (s == 0) fetch_kind<KS[0], NV>(J.src[0], off, v);
+                    else if (s == 1) fetch_kind<KS[1], NV>(J.src[1], off, v);
+                    else fetch_kind<KS[2], NV>(J.src[2], off, v);
+                    if (s == 0) run_chain<NV, KindOf<KS[0]>::dim>(J.src[0], v, c);
+                    else if (s == 1) run_chain<NV, KindOf<KS[1]>::dim>(J.src[1], v, c);
+                    else run_chain<NV, KindOf<KS[2]>::dim>(J.src[2], v, c);
+                    accumulate(u, s, blend<NV>(c, wts[u]));
+                }
             }
-            mix_finish(S[u], E[u]);
+        } else {
+            // every load of U scan points first, then chains, interpolation, classification
+            float vals[U][3][NV][4];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int off[NV];
+                if (NS > 0) {
+                    corner_offsets<INTERP>(J.src[0], dims, i0[u], off);
+                    fetch_kind<K0, NV>(J.src[0], off, vals[u][0]);
+                }
+                if (NS > 1) {
+                    corner_offsets<INTERP>(J.src[1], dims, i0[u], off);
+                    fetch_kind<K1, NV>(J.src[1], off, vals[u][1]);
+                }
+                if (NS > 2) {
+                    corner_offsets<INTERP>(J.src[2], dims, i0[u], off);
+                    fetch_kind<K2, NV>(J.src[2], off, vals[u][2]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    float c[NV];
+                    if (s == 0) run_chain<NV, KindOf<KS[0]>::dim>(J.src[0], vals[u][0], c);
+                    else if (s == 1) run_chain<NV, KindOf<KS[1]>::dim>(J.src[1], vals[u][1], c);
+                    else run_chain<NV, KindOf<KS[2]>::dim>(J.src[2], vals[u][2], c);
+                    accumulate(u, s, blend<NV>(c, wts[u]));
+                }
+            }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) mix_finish(S[u], E[u]);
     }
 }
 
 // One lane per ray: classical front-to-back compositing, U scan points per
 // step, early termination at the first point whose opacity reaches ert.
-template <int INTERP, int U, int SIG>
+template <int INTERP, int U, int SIG, bool PS>
 __device__ __forceinline__ void march_seq(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                           float4& out, int& count) {
     const float ert = J.ert;
@@ -551,7 +581,7 @@ __device__ __forceinline__ void march_seq(const DevJob& J, const float4* __restr
     bool done = false;
     for (int k = R.kb; k < R.ke && !done; k += U) {
         float E[U][3], S[U];
-        points<INTERP, U, SIG>(J, s_tf, R, k, E, S);
+        points<INTERP, U, SIG, PS>(J, s_tf, R, k, E, S);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (k + u < R.ke && !done) {
@@ -582,7 +612,7 @@ __device__ __forceinline__ float row_shr(float x) {
 // A + (1-A) A') across the group, then appended to the ray's running state.
 // The first point whose cumulative opacity reaches ert ends the ray, exactly
 // where the one-lane loop would stop.
-template <int INTERP, int G, int SIG>
+template <int INTERP, int G, int SIG, bool PS>
 __device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                             int lane, float4& out, int& count) {
     const int g = lane & (G - 1);
@@ -594,7 +624,7 @@ __device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __res
         const int k = k0 + g;
         const bool valid = k < R.ke;
         float E[1][3], S[1];
-        points<INTERP, 1, SIG>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
+        points<INTERP, 1, SIG, PS>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
         float c0 = valid ? E[0][0] : 0.f, c1 = valid ? E[0][1] : 0.f, c2 = valid ? E[0][2] : 0.f;
         float a = valid ? S[0] : 0.f;
 #pragma unroll
@@ -638,22 +668,22 @@ __device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __res
     count = n;
 }
 
-template <int INTERP, int U, int G, int SIG>
+template <int INTERP, int U, int G, int SIG, bool PS>
 __device__ __forceinline__ void march_sig(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                           int lane, float4& out, int& count) {
-    if constexpr (G == 1) march_seq<INTERP, (SIG == SIG_GENERIC ? 1 : U), SIG>(J, s_tf, R, out, count);
-    else march_lanes<INTERP, G, SIG>(J, s_tf, R, lane, out, count);
+    if constexpr (G == 1) march_seq<INTERP, (SIG == SIG_GENERIC ? 1 : U), SIG, PS>(J, s_tf, R, out, count);
+    else march_lanes<INTERP, G, SIG, PS>(J, s_tf, R, lane, out, count);
 }
 
-template <int INTERP, int U, int G>
+template <int INTERP, int U, int G, bool PS>
 __device__ __forceinline__ void march_dispatch(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                                int lane, float4& out, int& count) {
     switch (J.sig) {
-    case SIG_F32x1: march_sig<INTERP, U, G, SIG_F32x1>(J, s_tf, R, lane, out, count); break;
-    case SIG_PIC3_F32: march_sig<INTERP, U, G, SIG_PIC3_F32>(J, s_tf, R, lane, out, count); break;
-    case SIG_PIC3_F16: march_sig<INTERP, U, G, SIG_PIC3_F16>(J, s_tf, R, lane, out, count); break;
-    case SIG_PIC3_BF16: march_sig<INTERP, U, G, SIG_PIC3_BF16>(J, s_tf, R, lane, out, count); break;
-    default: march_sig<INTERP, U, G, SIG_GENERIC>(J, s_tf, R, lane, out, count); break;
+    case SIG_F32x1: march_sig<INTERP, U, G, SIG_F32x1, PS>(J, s_tf, R, lane, out, count); break;
+    case SIG_PIC3_F32: march_sig<INTERP, U, G, SIG_PIC3_F32, PS>(J, s_tf, R, lane, out, count); break;
+    case SIG_PIC3_F16: march_sig<INTERP, U, G, SIG_PIC3_F16, PS>(J, s_tf, R, lane, out, count); break;
+    case SIG_PIC3_BF16: march_sig<INTERP, U, G, SIG_PIC3_BF16, PS>(J, s_tf, R, lane, out, count); break;
+    default: march_sig<INTERP, U, G, SIG_GENERIC, PS>(J, s_tf, R, lane, out, count); break;
     }
 }
 
@@ -680,9 +710,12 @@ __device__ __forceinline__ bool pixel_of(const DevJob& J, int t, int lane, int w
     return px < J.width && py < J.height;
 }
 
-// Waves-per-SIMD hint: W = 0 leaves register allocation to the compiler,
-// W > 0 asks for at least W resident waves per SIMD (fewer registers each).
-template <int U, int G, int W>
+// Waves-per-SIMD hint: W = 0 leaves register allocation to the compiler and
+// issues every load of a scan point at once; W > 0 asks for at least W
+// resident waves per SIMD and evaluates the sources one after another.
+// SIGK >= 0: the kernel runs only that source signature (every job of the
+// launch has it); SIGK < 0: it dispatches on each job's signature.
+template <int U, int G, int W, int SIGK>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, 8)))
 void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ tf_pool, int* __restrict__ cursor,
                     int n_jobs, int total_tiles, int persistent) {
@@ -723,8 +756,13 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
         int count = 0;
         if (hit) {
-            if (J.interp) march_dispatch<1, U, G>(J, s_tf, R, lane, c, count);
-            else march_dispatch<0, U, G>(J, s_tf, R, lane, c, count);
+            if constexpr (SIGK < 0) {
+                if (J.interp) march_dispatch<1, U, G, (W > 0)>(J, s_tf, R, lane, c, count);
+                else march_dispatch<0, U, G, (W > 0)>(J, s_tf, R, lane, c, count);
+            } else {
+                if (J.interp) march_sig<1, U, G, SIGK, (W > 0)>(J, s_tf, R, lane, c, count);
+                else march_sig<0, U, G, SIGK, (W > 0)>(J, s_tf, R, lane, c, count);
+            }
         }
         if (in_image && (lane & (G - 1)) == 0) {
             const size_t pix = (size_t)py * J.width + px;
@@ -767,19 +805,45 @@ __global__ void strided_copy_kernel(CopyArgs a) {
 
 }  // namespace
 
+using KernelFn = void (*)(const DevJob*, const float4*, int*, int, int, int);
+
+template <int SIGK>
+KernelFn pick_specialized(int unroll, int lanes, int hint) {
+    if (unroll >= 2) return raycast_kernel<2, 1, 0, SIGK>;
+    switch (lanes) {
+    case 16: return hint ? raycast_kernel<1, 16, 4, SIGK> : raycast_kernel<1, 16, 0, SIGK>;
+    case 8: return hint ? raycast_kernel<1, 8, 4, SIGK> : raycast_kernel<1, 8, 0, SIGK>;
+    case 4: return hint ? raycast_kernel<1, 4, 4, SIGK> : raycast_kernel<1, 4, 0, SIGK>;
+    case 2: return raycast_kernel<1, 2, 0, SIGK>;
+    default: return hint ? raycast_kernel<1, 1, 4, SIGK> : raycast_kernel<1, 1, 0, SIGK>;
+    }
+}
+
+KernelFn pick_kernel(int sig, int unroll, int lanes, int hint) {
+    switch (sig) {
+    case SIG_F32x1: return pick_specialized<SIG_F32x1>(unroll, lanes, hint);
+    case SIG_PIC3_F32: return pick_specialized<SIG_PIC3_F32>(unroll, lanes, hint);
+    case SIG_PIC3_F16: return pick_specialized<SIG_PIC3_F16>(unroll, lanes, hint);
+    case SIG_PIC3_BF16: return pick_specialized<SIG_PIC3_BF16>(unroll, lanes, hint);
+    default:
+        break;
+    }
+    // mixed or generic signatures: the dispatching kernels (one lane-count each)
+    switch (lanes) {
+    case 16: return raycast_kernel<1, 16, 0, -1>;
+    case 8: return raycast_kernel<1, 8, 0, -1>;
+    case 4: return raycast_kernel<1, 4, 0, -1>;
+    case 2: return raycast_kernel<1, 2, 0, -1>;
+    default: return raycast_kernel<1, 1, 0, -1>;
+    }
+}
+
 int launch_raycast(const LaunchArgs& a, void* stream) {
     // dynamic LDS: one 256-entry RGBA32F table per active source of the widest job
     const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfEntries * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
     if (blocks == 0) return hipSuccess;
-    auto* kernel = raycast_kernel<1, 1, 0>;
-    switch (a.lanes) {
-    case 16: kernel = a.waves_hint ? raycast_kernel<1, 16, 4> : raycast_kernel<1, 16, 0>; break;
-    case 8: kernel = a.waves_hint ? raycast_kernel<1, 8, 4> : raycast_kernel<1, 8, 0>; break;
-    case 4: kernel = a.waves_hint ? raycast_kernel<1, 4, 4> : raycast_kernel<1, 4, 0>; break;
-    case 2: kernel = raycast_kernel<1, 2, 0>; break;
-    default: kernel = a.unroll >= 2 ? raycast_kernel<2, 1, 0> : (a.waves_hint ? raycast_kernel<1, 1, 4> : raycast_kernel<1, 1, 0>);
-    }
+    const KernelFn kernel = pick_kernel(a.sig, a.unroll, a.lanes, a.waves_hint);
     hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlockThreads), lds, (hipStream_t)stream, a.jobs,
                        reinterpret_cast<const float4*>(a.tf_pool), a.cursor, a.n_jobs, a.total_tiles, a.persistent);
     return hipGetLastError();
@@ -813,7 +877,7 @@ int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, 
 }
 
 int raycast_occupancy(int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, raycast_kernel<1, 1, 0>, kBlockThreads,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, raycast_kernel<1, 1, 0, -1>, kBlockThreads,
                                                        3 * kTfEntries * sizeof(float4));
 }
 

@@ -123,6 +123,8 @@ class DeviceExecutor(Executor):
         self.handles: Dict[tuple, int] = {}
         self.refs: Dict[int, int] = collections.Counter()
         self.ticket_handles: Dict[int, list] = {}
+        self.latest: Dict[tuple, tuple] = {}          # (client, source) -> newest table key
+        self.submits = 0
 
     def camera(self, direction):
         c = np.array(self.dims, dtype=np.float64) / 2.0
@@ -150,6 +152,11 @@ class DeviceExecutor(Executor):
 
     def submit(self, jobs):
         descs, hss = zip(*[self.desc(j) for j in jobs])
+        for j in jobs:
+            for key in j.tf_key:
+                cs = key[:2]
+                if cs not in self.latest or self.latest[cs][2] < key[2]:
+                    self.latest[cs] = key
         tickets = self.ctx.submit_batch(list(descs))
         if tickets is None:
             return None
@@ -157,6 +164,9 @@ class DeviceExecutor(Executor):
             self.ticket_handles[t] = hs
             for h in hs:
                 self.refs[h] += 1
+        self.submits += 1
+        if self.submits % 64 == 0:
+            self.retire_tables(set(self.latest.values()))
         return tickets
 
     def poll(self, ticket):
@@ -172,7 +182,8 @@ class DeviceExecutor(Executor):
             self.refs[h] -= 1
 
     def retire_tables(self, live_keys):
-        """Release tables no client uses any more and no ticket holds."""
+        """Release tables no client uses any more and no ticket holds (the library
+        reuses a released slot only after every render reading it has finished)."""
         for key in [k for k in self.handles if k not in live_keys]:
             h = self.handles[key]
             if self.refs[h] == 0:

@@ -1,0 +1,94 @@
+"""Serving: requests batched on arrival give the same image as each request rendered alone."""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import compare, log
+from scenes import configs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1611_09048_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(device=0, mem_budget=64 << 20, max_inflight=24)
+    yield c
+    c.close()
+
+
+def test_served_images_equal_alone_renders(ctx):
+    import torch
+    from paper_1611_09048_amd import device, serve
+    dims = (48, 40, 36)
+    vol_scene = configs.pic3(dims=dims, width=8, height=8)
+    vol = device.upload_volume(ctx, vol_scene, 7)
+    ex = serve.DeviceExecutor(ctx, vol, dims)
+    images = {}
+    jobs = {}
+
+    def on_done(rec, ticket):
+        h, w = rec.height, rec.width
+        images[rec.rid] = ctx.read_image(ticket, np.empty((h, w, 4), dtype=np.float32))
+
+    srv = serve.Server(ex, time.perf_counter, max_batch=6, max_batches_in_flight=3, on_done=on_done)
+    reqs = configs.serving_requests(21, dims, n_clients=3, rate_per_client=400.0, duration=0.12,
+                                    base_tfs=[s.tf for s in vol_scene.sources])
+    reqs = [r.__class__(**{**r.__dict__, "width": (64, 97, 130)[i % 3], "height": (64, 55, 71)[i % 3]})
+            for i, r in enumerate(reqs)]
+
+    def make_job(i, r):
+        j = serve.job_from_request(i, r)
+        jobs[i] = j
+        return j
+
+    dur = serve.run(srv, reqs, time.perf_counter, make_job=make_job)
+    s = srv.summary(dur)
+    log("serving test summary", s)
+    assert s["completed"] == len(reqs) and s["failed"] == 0
+    assert s["batches"] < len(reqs)                 # requests were batched
+    used, budget, inflight = ctx.serving_usage()
+    assert inflight == 0 and used == 0
+    # each request alone, through isaac_render, with the same descriptor
+    for rid, j in jobs.items():
+        desc, _ = ex.desc(j)
+        out = torch.full((j.height, j.width, 4), float("nan"), dtype=torch.float32, device="cuda")
+        desc.out_rgba = out.data_ptr()
+        ctx.render([desc])
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), images[rid]), rid
+    # and a few against the oracle
+    for rid in list(jobs)[:3]:
+        j = jobs[rid]
+        eye, center, up = ex.camera(j.direction)
+        from scenes.layout import Camera
+        srcs = [s.__class__(**{**s.__dict__, "tf": j.tfs[k]}) for k, s in enumerate(vol_scene.sources)]
+        sc = vol_scene.with_(sources=srcs, camera=Camera(eye=eye, center=center, up=up), width=j.width,
+                             height=j.height, clip=j.clip)
+        compare(images[rid].reshape(-1, 4), None, oracle.render(sc), label=f"served request {rid}")
+    del vol
+
+
+def test_admission_refused_when_budget_is_full(ctx):
+    from paper_1611_09048_amd import device
+    sc = configs.pic3(n=16, width=1024, height=1024)
+    vol = device.upload_volume(ctx, sc, 8)
+    job = device.render_job(sc, 8, device.new_image(sc))
+    tickets = []
+    while True:
+        t = ctx.submit(job)
+        if t is None:
+            break
+        tickets.append(t)
+        assert len(tickets) <= 4
+    assert len(tickets) == 4               # 64 MiB budget / 16 MiB images
+    for t in tickets:
+        ctx.release(t)
+    assert ctx.serving_usage()[0] == 0
+    assert ctx.submit(job) is not None
+    del vol
