@@ -72,9 +72,16 @@ def cpu_baseline(scene, gpu_counts, row_stride: int, threads: int):
                        f"on {agree * 100:.2f}% of them")
 
 
+FORCED_SHAPE = None
+
+
 def apply_tuning(ctx, key_sig, classes, time_jobs, retune=False):
     """Set the tile shape of `classes` from the cache, tuning (one shape for all) when missing."""
     from paper_1611_09048_amd import autotune
+    if FORCED_SHAPE is not None:
+        for c in classes:
+            ctx.set_tile_shape(c, *FORCED_SHAPE)
+        return FORCED_SHAPE
     cache = autotune.load_cache(TUNED)
     key = autotune.cache_key("gfx950", "+".join(map(str, classes)), key_sig)
     if key in cache and not retune:
@@ -248,7 +255,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--shape", default="", help="wave_w,waves_x,unroll,lanes,min_waves instead of the tuned shape")
     args = ap.parse_args()
+    if args.shape:
+        global FORCED_SHAPE
+        FORCED_SHAPE = tuple(int(v) for v in args.shape.split(","))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): every job of this ray caster is "
               f"rendered by one GPU and there is no multi-GPU path in this build", file=sys.stderr)

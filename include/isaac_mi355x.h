@@ -161,6 +161,18 @@ typedef struct {
     float* out_rgba;                  /* device, CALLER-OWNED, height*width*4 floats, premultiplied, row 0 = top */
     int32_t* out_samples;             /* device or NULL: per-pixel count of composited samples */
     void* update_pointer;             /* passed as `pointer` to every source's update() */
+    /* Brick of a larger volume (sort-last rendering, Sec. 3.1): when
+     * brick_origin is not NULL the camera and clip planes are in the global
+     * index space [0, global_dims], the step grid is anchored at the entry into
+     * the global box, and this volume (voxel (0,0,0) at brick_origin) renders
+     * only the scan points inside its own box.  Neighbouring bricks split every
+     * ray's scan points without overlap; isaac_composite combines the partial
+     * images.  Use ert_threshold > 1 for bricks: termination needs the opacity
+     * in front, which a brick does not know. */
+    const int32_t* brick_origin;      /* host, 3 ints, or NULL */
+    const int32_t* global_dims;       /* host, 3 ints (required with brick_origin) */
+    float* out_depth;                 /* device or NULL: per pixel, ray parameter of the first scan point
+                                         (+inf where there is none), the compositing order */
 } isaac_render_desc;
 
 /* Ray-cast jobs (all validated before any launch).  One job is one kernel
@@ -168,6 +180,15 @@ typedef struct {
  * shared tile queue, replayed as a hipGraph unless ISAAC_NO_GRAPH.  Without
  * ISAAC_ASYNC the call returns after the images are complete. */
 isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags);
+
+/* Sort-last compositing (Sec. 3.1, Fig. "whole concept"): per pixel, order the
+ * n_layers partial images by their depth images (out_depth of the brick
+ * renders) and combine them front to back:
+ * (C, A) o (C', A') = (C + (1-A) C', A + (1-A) A').  rgba and depth are host
+ * arrays of n_layers device pointers (1..16); out is device RGBA32F.  Runs on
+ * the context stream; without ISAAC_ASYNC it waits for the result. */
+isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const float* const* depth, int n_layers,
+                             int width, int height, float* out, unsigned flags);
 
 /* Sum and count of the kernel durations of ISAAC_TIMING renders since the
  * last call (waits for them), then resets. */

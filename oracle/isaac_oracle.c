@@ -355,6 +355,39 @@ static double source_value(const prepared* P, int s, int x, int y, int z) {
     return apply_chain(&P->ch[s], v, NULL);
 }
 
+/* The (interpolated) chain output of source s at position p. */
+static double source_at(const prepared* P, int s, const double p[3], const int* cell) {
+    const oracle_scene* sc = P->sc;
+    const oracle_source* src = &sc->src[s];
+    if (sc->interpolation == 0) {
+        int q[3];
+        for (int a = 0; a < 3; a++)
+            q[a] = cell ? cell[a] : clamp_int((int)floor(p[a]), 0, sc->dims[a] - 1);
+        return source_value(P, s, q[0], q[1], q[2]);
+    }
+    int i0[3];
+    double f[3];
+    for (int a = 0; a < 3; a++) {
+        double u = p[a] - 0.5;
+        double fl = floor(u);
+        i0[a] = (int)fl;
+        f[a] = u - fl;
+    }
+    double x = 0.0;
+    for (int corner = 0; corner < 8; corner++) {
+        int q[3];
+        double w = 1.0;
+        for (int a = 0; a < 3; a++) {
+            int bit = (corner >> a) & 1;
+            q[a] = i0[a] + bit;
+            if (src->guard < 1) q[a] = clamp_int(q[a], 0, sc->dims[a] - 1);
+            w *= bit ? f[a] : 1.0 - f[a];
+        }
+        x += w * source_value(P, s, q[0], q[1], q[2]);
+    }
+    return x;
+}
+
 /* One scan point at position p: combined premultiplied colour E and opacity S.
  * cell, when not NULL, overrides the nearest cell (for the flip allowance). */
 static void scan_point(const prepared* P, const double p[3], const int* cell, double E[3], double* S) {
@@ -363,34 +396,7 @@ static void scan_point(const prepared* P, const double p[3], const int* cell, do
     for (int s = 0; s < sc->n_src; s++) {
         const oracle_source* src = &sc->src[s];
         if (!src->enabled) continue;                  /* never read */
-        double x;
-        if (sc->interpolation == 0) {
-            int q[3];
-            for (int a = 0; a < 3; a++)
-                q[a] = cell ? cell[a] : clamp_int((int)floor(p[a]), 0, sc->dims[a] - 1);
-            x = source_value(P, s, q[0], q[1], q[2]);
-        } else {
-            int i0[3];
-            double f[3];
-            for (int a = 0; a < 3; a++) {
-                double u = p[a] - 0.5;
-                double fl = floor(u);
-                i0[a] = (int)fl;
-                f[a] = u - fl;
-            }
-            x = 0.0;
-            for (int corner = 0; corner < 8; corner++) {
-                int q[3];
-                double w = 1.0;
-                for (int a = 0; a < 3; a++) {
-                    int bit = (corner >> a) & 1;
-                    q[a] = i0[a] + bit;
-                    if (src->guard < 1) q[a] = clamp_int(q[a], 0, sc->dims[a] - 1);
-                    w *= bit ? f[a] : 1.0 - f[a];
-                }
-                x += w * source_value(P, s, q[0], q[1], q[2]);
-            }
-        }
+        double x = source_at(P, s, p, cell);
         double rgba[4];
         classify(P->table[s], x, rgba);
         double wa = src->weight * rgba[3];
@@ -430,6 +436,26 @@ static int nearest_flags(const prepared* P, const double p[3], int cell[3], int 
     return mask;
 }
 
+/* The scan point grid: t_k = t0 + (k + 1/2) step. */
+static double scan_param(const oracle_scene* sc, double t0, int64_t k) {
+    return t0 + ((double)k + 0.5) * sc->step;
+}
+
+/* Clipping: keep p iff n.p + d >= 0 for every plane; *near_plane is set when
+ * p lies within delta of some plane. */
+static int clip_keep(const oracle_scene* sc, const double p[3], int* near_plane) {
+    int keep = 1;
+    *near_plane = 0;
+    for (int c = 0; c < sc->n_clip; c++) {
+        const double* pl = sc->clip + 4 * c;
+        double s = pl[0] * p[0] + pl[1] * p[1] + pl[2] * p[2] + pl[3];
+        double nn = sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+        if (s < 0.0) keep = 0;
+        if (fabs(s) < sc->delta * nn) *near_plane = 1;
+    }
+    return keep;
+}
+
 static void render_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
     const oracle_scene* sc = P->sc;
     memset(px, 0, sizeof(*px));
@@ -441,20 +467,13 @@ static void render_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
     int flags = 0, kinds = 0;
     const double delta = sc->delta;
     for (int64_t k = 0;; k++) {
-        double t = t0 + ((double)k + 0.5) * sc->step;
+        double t = scan_param(sc, t0, k);
         int inside = t < t1;
         if (!inside && !(t - t1 < delta)) break;
         double p[3];
         for (int a = 0; a < 3; a++) p[a] = o[a] + t * d[a];
-        int keep = inside;
-        int near_plane = 0;
-        for (int c = 0; c < sc->n_clip; c++) {
-            const double* pl = sc->clip + 4 * c;
-            double s = pl[0] * p[0] + pl[1] * p[1] + pl[2] * p[2] + pl[3];
-            double nn = sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
-            if (s < 0.0) keep = 0;
-            if (fabs(s) < delta * nn) near_plane = 1;
-        }
+        int near_plane;
+        int keep = clip_keep(sc, p, &near_plane) && inside;
         int near_exit = (t1 - t < delta) && (t - t1 < delta);
         int kind = (near_plane ? ORACLE_FLAG_CLIP : 0) | (near_exit ? ORACLE_FLAG_EXIT : 0);
         double T = 1.0 - A;                          /* transmittance before this point */
@@ -521,6 +540,86 @@ static void render_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
     px->kinds = kinds;
 }
 
+/* ------------------------------------------------------------------ */
+/* iso-surface rendering (a listed feature, Sec. 3; no algorithm given): */
+/* the surface is the first place along the ray where a source's        */
+/* interpolated chain output crosses its iso value between two          */
+/* consecutive kept scan points; the crossing is placed by linear        */
+/* interpolation, the normal is the central-difference gradient (half a  */
+/* voxel), and the opaque pixel is the TF colour at the iso value lit by */
+/* a headlight: rgb * (0.3 + 0.7 |n . d|), opacity 1.                    */
+/* ------------------------------------------------------------------ */
+static void iso_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
+    const oracle_scene* sc = P->sc;
+    memset(px, 0, sizeof(*px));
+    double o[3], d[3], t0, t1;
+    pixel_ray(P, i, j, o, d);
+    if (!box_interval(P, o, d, &t0, &t1)) return;
+    const double delta = sc->delta;
+    double prev[MAX_SRC];
+    double t_prev = 0.0;
+    int have_prev = 0;
+    for (int64_t k = 0;; k++) {
+        double t = scan_param(sc, t0, k);
+        if (!(t < t1)) {
+            if (t - t1 < delta) { px->kinds |= ORACLE_FLAG_EXIT; px->flags++; }
+            break;
+        }
+        if (t1 - t < delta) { px->kinds |= ORACLE_FLAG_EXIT; px->flags++; }
+        double p[3];
+        for (int a = 0; a < 3; a++) p[a] = o[a] + t * d[a];
+        int near_plane;
+        int keep = clip_keep(sc, p, &near_plane);
+        if (near_plane) { px->kinds |= ORACLE_FLAG_CLIP; px->flags++; }
+        if (!keep) {
+            have_prev = 0;
+            continue;
+        }
+        if (sc->interpolation == 0) {
+            int cell[3], alt[3];
+            if (nearest_flags(P, p, cell, alt)) { px->kinds |= ORACLE_FLAG_NEAREST; px->flags++; }
+        }
+        px->samples++;
+        double x[MAX_SRC] = {0};
+        int hit = -1;
+        double f = 0.0;
+        for (int s = 0; s < sc->n_src; s++) {
+            const oracle_source* src = &sc->src[s];
+            if (!src->enabled || isnan(src->iso)) continue;
+            x[s] = source_at(P, s, p, NULL);
+            if (fabs(x[s] - src->iso) < sc->iso_margin) { px->kinds |= ORACLE_FLAG_ISO; px->flags++; }
+            if (hit < 0 && have_prev && ((prev[s] >= src->iso) != (x[s] >= src->iso))) {
+                hit = s;
+                f = (src->iso - prev[s]) / (x[s] - prev[s]);
+            }
+        }
+        if (hit >= 0) {
+            const oracle_source* src = &sc->src[hit];
+            double ts = t_prev + f * (t - t_prev), q[3], g[3];
+            for (int a = 0; a < 3; a++) q[a] = o[a] + ts * d[a];
+            for (int a = 0; a < 3; a++) {
+                double qp[3] = {q[0], q[1], q[2]}, qm[3] = {q[0], q[1], q[2]};
+                qp[a] += 0.5;
+                qm[a] -= 0.5;
+                g[a] = source_at(P, hit, qp, NULL) - source_at(P, hit, qm, NULL);
+            }
+            double gl = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+            double cosine = gl > 0.0 ? fabs(g[0] * d[0] + g[1] * d[1] + g[2] * d[2]) / gl : 1.0;
+            double rgba[4];
+            classify(P->table[hit], src->iso, rgba);
+            double light = 0.3 + 0.7 * cosine;
+            for (int c = 0; c < 3; c++) px->rgba[c] = rgba[c] * light;
+            px->rgba[3] = 1.0;
+            break;
+        }
+        for (int s = 0; s < sc->n_src; s++) prev[s] = x[s];
+        t_prev = t;
+        have_prev = 1;
+    }
+    /* a decision within the margins may go either way: the pixel is unconstrained */
+    if (px->flags) px->allowance = 2.0;
+}
+
 static int check_scene(const oracle_scene* sc, char* err, int errlen) {
     for (int s = 0; s < sc->n_src; s++) {
         const oracle_source* src = &sc->src[s];
@@ -548,7 +647,8 @@ int oracle_render_range(const oracle_scene* sc, int64_t first, int64_t count, or
             free(P);
             return fail(err, errlen, "pixel index out of range");
         }
-        render_pixel(P, (int)(idx % sc->width), (int)(idx / sc->width), &out[q]);
+        if (sc->mode == 1) iso_pixel(P, (int)(idx % sc->width), (int)(idx / sc->width), &out[q]);
+        else render_pixel(P, (int)(idx % sc->width), (int)(idx / sc->width), &out[q]);
     }
     free(P);
     return 0;
@@ -568,7 +668,8 @@ int oracle_render_list(const oracle_scene* sc, const int32_t* px, int64_t n, ora
             free(P);
             return fail(err, errlen, "pixel (%d,%d) outside the image", i, j);
         }
-        render_pixel(P, i, j, &out[q]);
+        if (sc->mode == 1) iso_pixel(P, i, j, &out[q]);
+        else render_pixel(P, i, j, &out[q]);
     }
     free(P);
     return 0;

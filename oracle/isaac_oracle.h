@@ -43,6 +43,7 @@ typedef struct {
     int enabled;                      /* 0: never read */
     int n_tf;                         /* number of transfer-function control points */
     const double* tf;                 /* n_tf * 5 doubles: x r g b a */
+    double iso;                       /* iso-surface mode: the source's iso value (NaN: no surface) */
 } oracle_source;
 
 typedef struct {
@@ -58,6 +59,8 @@ typedef struct {
     int n_clip;
     const double* clip;               /* n_clip * 4: nx ny nz d, keep n.x + d >= 0 */
     double ert_threshold;             /* stop once accumulated opacity >= this (> 1: never) */
+    int mode;                         /* 0 volume rendering, 1 iso-surface rendering */
+    double iso_margin;                /* iso mode: values this close to the iso value flag the pixel */
     double delta;                     /* decision margin for the flip allowance (voxels) */
     double ert_margin;                /* opacity margin for the flip allowance at the threshold */
 } oracle_scene;
@@ -72,7 +75,7 @@ typedef struct {
     int32_t pad;
 } oracle_pixel;
 
-enum { ORACLE_FLAG_NEAREST = 1, ORACLE_FLAG_CLIP = 2, ORACLE_FLAG_EXIT = 4, ORACLE_FLAG_ERT = 8 };
+enum { ORACLE_FLAG_NEAREST = 1, ORACLE_FLAG_CLIP = 2, ORACLE_FLAG_EXIT = 4, ORACLE_FLAG_ERT = 8, ORACLE_FLAG_ISO = 16 };
 
 /* Render pixels [first, first+count) of the row-major image (row 0 at the top).
  * Returns 0, or -1 with a message in err. */

@@ -25,7 +25,8 @@ class _Source(ctypes.Structure):
     _fields_ = [("f_dim", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("comp", ctypes.c_void_p * 4), ("stride", ctypes.c_int64 * 3),
                 ("guard", ctypes.c_int), ("chain", ctypes.c_char_p), ("weight", ctypes.c_double),
-                ("enabled", ctypes.c_int), ("n_tf", ctypes.c_int), ("tf", ctypes.POINTER(ctypes.c_double))]
+                ("enabled", ctypes.c_int), ("n_tf", ctypes.c_int), ("tf", ctypes.POINTER(ctypes.c_double)),
+                ("iso", ctypes.c_double)]
 
 
 class _Scene(ctypes.Structure):
@@ -36,17 +37,19 @@ class _Scene(ctypes.Structure):
                 ("width", ctypes.c_int), ("height", ctypes.c_int), ("step", ctypes.c_double),
                 ("interpolation", ctypes.c_int), ("n_clip", ctypes.c_int),
                 ("clip", ctypes.POINTER(ctypes.c_double)), ("ert_threshold", ctypes.c_double),
+                ("mode", ctypes.c_int), ("iso_margin", ctypes.c_double),
                 ("delta", ctypes.c_double), ("ert_margin", ctypes.c_double)]
 
 
 PIXEL_DTYPE = np.dtype([("rgba", np.float64, 4), ("samples", np.int64), ("allowance", np.float64),
                         ("flags", np.int32), ("kinds", np.int32), ("count_slack", np.int32), ("pad", np.int32)])
 assert PIXEL_DTYPE.itemsize == 64
-FLAG_NEAREST, FLAG_CLIP, FLAG_EXIT, FLAG_ERT = 1, 2, 4, 8
+FLAG_NEAREST, FLAG_CLIP, FLAG_EXIT, FLAG_ERT, FLAG_ISO = 1, 2, 4, 8, 16
 NO_TERMINATION = 2.0        # a threshold opacity never reaches
 
 DELTA = 2.0 ** -12          # voxels: decisions closer than this may go either way on the GPU
 ERT_MARGIN = 1e-4           # opacity margin around the termination threshold
+ISO_MARGIN = 1e-3           # iso mode: values this close to the iso value may cross on either side
 
 _lib = None
 _lock = threading.Lock()
@@ -120,6 +123,7 @@ class _Marshalled:
             self.keep.append(tf)
             cs.n_tf = len(s.tf)
             cs.tf = tf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            cs.iso = float(s.iso)
         sc = _Scene()
         sc.dims[:] = [int(v) for v in scene.dims]
         sc.n_src = n
@@ -141,6 +145,8 @@ class _Marshalled:
         sc.n_clip = len(scene.clip)
         sc.clip = clip.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         sc.ert_threshold = float(scene.ert_threshold if ert_threshold is None else ert_threshold)
+        sc.mode = {"volume": 0, "iso": 1}[scene.mode]
+        sc.iso_margin = ISO_MARGIN
         sc.delta = float(delta)
         sc.ert_margin = float(ert_margin)
         self.scene = sc

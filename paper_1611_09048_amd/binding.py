@@ -63,11 +63,13 @@ class RenderDesc(ctypes.Structure):
                 ("clip", ctypes.POINTER(ClipPlane)), ("tf_handles", ctypes.POINTER(ctypes.c_int32)),
                 ("weights", ctypes.POINTER(ctypes.c_float)), ("enabled", ctypes.POINTER(ctypes.c_int32)),
                 ("ert_threshold", ctypes.c_float), ("out_rgba", ctypes.c_void_p),
-                ("out_samples", ctypes.c_void_p), ("update_pointer", ctypes.c_void_p)]
+                ("out_samples", ctypes.c_void_p), ("update_pointer", ctypes.c_void_p),
+                ("brick_origin", ctypes.POINTER(ctypes.c_int32)), ("global_dims", ctypes.POINTER(ctypes.c_int32)),
+                ("out_depth", ctypes.c_void_p)]
 
 
 EXPORTS = ["isaac_init", "isaac_destroy", "isaac_last_error", "isaac_init_error", "isaac_set_sources",
-           "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_timing",
+           "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_composite", "isaac_timing",
            "isaac_set_tile_shape", "isaac_get_tile_shape", "isaac_submit", "isaac_submit_batch", "isaac_poll",
            "isaac_release", "isaac_read_image", "isaac_serving_usage", "isaac_check_functor_chain", "isaac_version"]
 
@@ -99,6 +101,8 @@ def load(path: Optional[str] = None):
     lib.isaac_release_transfer.argtypes = [c_ctx, ctypes.c_int32]
     lib.isaac_render.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.c_int, ctypes.c_uint]
     lib.isaac_timing.argtypes = [c_ctx, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.isaac_composite.argtypes = [c_ctx, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint]
     lib.isaac_set_tile_shape.argtypes = [c_ctx] + [ctypes.c_int] * 6
     lib.isaac_get_tile_shape.argtypes = [c_ctx, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 5
     lib.isaac_submit.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.POINTER(ctypes.c_uint64)]
@@ -196,6 +200,13 @@ class Context:
         arr = (RenderDesc * len(jobs))(*jobs)
         self._check(self.lib.isaac_render(self.h, arr, len(jobs), flags))
 
+    def composite(self, rgba_ptrs, depth_ptrs, width: int, height: int, out_ptr: int, flags: int = 0):
+        """Sort-last over-compositing of partial images (device pointers) into out_ptr."""
+        n = len(rgba_ptrs)
+        r = (ctypes.c_void_p * n)(*rgba_ptrs)
+        d = (ctypes.c_void_p * n)(*depth_ptrs)
+        self._check(self.lib.isaac_composite(self.h, r, d, n, width, height, out_ptr, flags))
+
     def timing(self):
         ms, n = ctypes.c_double(), ctypes.c_int()
         self._check(self.lib.isaac_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
@@ -275,7 +286,8 @@ def source_desc(*, name: str, f_dim: int, dtype: str, comp: Sequence[int], strid
 def render_desc(*, volume_id: int, width: int, height: int, eye, center, up, fovy_deg: float = 60.0,
                 projection: int = PERSPECTIVE, ortho_height: float = 0.0, step: float = 0.5,
                 interpolation: int = NEAREST, clip=(), tf_handles=None, weights=None, enabled=None,
-                ert_threshold: float = 0.0, out_rgba: int = 0, out_samples: int = 0) -> RenderDesc:
+                ert_threshold: float = 0.0, out_rgba: int = 0, out_samples: int = 0, brick_origin=None,
+                global_dims=None, out_depth: int = 0) -> RenderDesc:
     j = RenderDesc()
     j.volume_id = volume_id
     j.width, j.height = width, height
@@ -310,5 +322,12 @@ def render_desc(*, volume_id: int, width: int, height: int, eye, center, up, fov
     j.ert_threshold = ert_threshold
     j.out_rgba = out_rgba or None
     j.out_samples = out_samples or None
+    if brick_origin is not None:
+        a = _arr(ctypes.c_int32, [int(v) for v in brick_origin])
+        b = _arr(ctypes.c_int32, [int(v) for v in global_dims])
+        keep.extend([a, b])
+        j.brick_origin = a
+        j.global_dims = b
+    j.out_depth = out_depth or None
     j._keep = keep          # arrays referenced by pointer stay alive with the struct
     return j

@@ -553,6 +553,24 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
         dj.clip[c][3] = p.d;
     }
     dj.ert = j.ert_threshold == 0.0f ? 0.999f : j.ert_threshold;
+    if (j.brick_origin) {
+        if (!j.global_dims) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "brick_origin needs global_dims");
+        for (int a = 0; a < 3; ++a) {
+            if (j.brick_origin[a] < 0 || j.global_dims[a] < 1 || j.brick_origin[a] + v.dims[a] > j.global_dims[a] ||
+                j.global_dims[a] > (1 << 22))
+                return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "brick axis %d lies outside the global box", a);
+            dj.org[a] = (float)j.brick_origin[a];
+            dj.gbox_hi[a] = (double)j.global_dims[a];
+        }
+        dj.brick = 1;
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            dj.org[a] = 0.0f;
+            dj.gbox_hi[a] = (double)v.dims[a];
+        }
+        dj.brick = 0;
+    }
+    dj.out_depth = j.out_depth;
     const TileShape& ts = ctx->shapes[size_class_of(j.width, j.height)];
     dj.wave_w = ts.wave_w;
     dj.waves_x = ts.waves_x;
@@ -1067,6 +1085,20 @@ isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int
     isaac_status st = check_ctx(ctx);
     if (st) return st;
     return render_impl(ctx, jobs, n_jobs, flags, true, ctx->stream);
+}
+
+isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const float* const* depth, int n_layers,
+                             int width, int height, float* out, unsigned flags) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (n_layers < 1 || n_layers > kMaxLayers || !rgba || !depth || !out || width < 1 || height < 1)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "composite needs 1..%d layers, pointers and a size", kMaxLayers);
+    for (int l = 0; l < n_layers; ++l)
+        if (!rgba[l] || !depth[l]) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "layer %d has a NULL pointer", l);
+    int rc = launch_composite(rgba, depth, n_layers, (int64_t)width * height, out, ctx->stream);
+    if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "composite launch: %s", hipGetErrorString((hipError_t)rc));
+    if (!(flags & ISAAC_ASYNC)) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return ISAAC_OK;
 }
 
 isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count) {

@@ -72,6 +72,9 @@ struct DevJob {
     double aspect;         // width / height
     double step;
     double clip[kMaxClip][4];
+    double gbox_hi[3];     // the global box [0, gbox_hi] the step grid is anchored to
+    float org[3];          // index of this volume's voxel (0,0,0) in the global box (bricks)
+    int32_t brick;         // 1: this volume is a brick of a larger global volume
     int32_t ortho;
     int32_t width, height;
     int32_t interp;
@@ -90,6 +93,7 @@ struct DevJob {
     int32_t tile_begin;    // first tile index of this job in the batch
     float* out;            // device RGBA32F image
     int32_t* out_samples;  // device per-pixel sample counts or null
+    float* out_depth;      // device per-pixel ray parameter of the first scan point (+inf: none) or null
     DevSource src[kMaxSources];
 };
 
@@ -115,5 +119,8 @@ int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, 
                         const int64_t* dst_stride, int esize, int f_dim, const int32_t lo[3],
                         const int32_t ext[3], void* stream);
 int raycast_occupancy(int* blocks_per_cu);
+constexpr int kMaxLayers = 16;
+int launch_composite(const float* const* rgba, const float* const* depth, int n_layers, int64_t n_pixels,
+                     float* out, void* stream);
 
 }  // namespace isaac

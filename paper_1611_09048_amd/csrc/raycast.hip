@@ -239,10 +239,19 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v,
 // point; otherwise the kept sample indices are [*kb, *ke) and the FP32 ray is
 // p(k) = pb + ((k + 1/2) * step) * d32.
 struct RaySetup {
-    float pb[3];
+    float pb[3];           // global position of the ray at t0
     float d[3];
     int kb, ke;
+    float t_first;         // ray parameter of scan point kb
 };
+
+// Scan point k in the volume's own index space: the global position minus the
+// brick origin (an exact FP32 subtraction of an integer below the position).
+__device__ __forceinline__ void point_at(const DevJob& J, const RaySetup& R, float tk, float (&p)[3]) {
+    p[0] = fmaf(tk, R.d[0], R.pb[0]) - J.org[0];
+    p[1] = fmaf(tk, R.d[1], R.pb[1]) - J.org[1];
+    p[2] = fmaf(tk, R.d[2], R.pb[2]) - J.org[2];
+}
 
 __device__ __forceinline__ bool setup_ray(const DevJob& J, int px, int py, RaySetup& R) {
 #pragma clang fp contract(off)
@@ -262,27 +271,46 @@ __device__ __forceinline__ bool setup_ray(const DevJob& J, int px, int py, RaySe
         const double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         for (int a = 0; a < 3; ++a) d[a] = d[a] / n;
     }
-    // slab test against [0, N]
-    double lo = -__builtin_inf(), hi = __builtin_inf();
-    for (int a = 0; a < 3; ++a) {
-        const double nn = (double)J.dims[a];
-        if (d[a] == 0.0) {
-            if (o[a] < 0.0 || o[a] > nn) return false;
-            continue;
+    // slab test against the box [lo_a, hi_a] per axis
+    auto slab = [&](const double* blo, const double* bhi, double& lo, double& hi) {
+#pragma clang fp contract(off)
+        lo = -__builtin_inf();
+        hi = __builtin_inf();
+        for (int a = 0; a < 3; ++a) {
+            if (d[a] == 0.0) {
+                if (o[a] < blo[a] || o[a] > bhi[a]) return false;
+                continue;
+            }
+            const double ta = (blo[a] - o[a]) / d[a];
+            const double tb = (bhi[a] - o[a]) / d[a];
+            const double tn = ta < tb ? ta : tb;
+            const double tf = ta < tb ? tb : ta;
+            if (tn > lo) lo = tn;
+            if (tf < hi) hi = tf;
         }
-        const double ta = (0.0 - o[a]) / d[a];
-        const double tb = (nn - o[a]) / d[a];
-        const double tn = ta < tb ? ta : tb;
-        const double tf = ta < tb ? tb : ta;
-        if (tn > lo) lo = tn;
-        if (tf < hi) hi = tf;
-    }
+        return true;
+    };
+    // the step grid is anchored at the entry into the global box
+    const double zero[3] = {0.0, 0.0, 0.0};
+    double lo, hi;
+    if (!slab(zero, J.gbox_hi, lo, hi)) return false;
     if (lo < 0.0) lo = 0.0;
     if (!(hi > lo)) return false;
     const double t0 = lo, t1 = hi, step = J.step;
     // scan points t_k = t0 + (k + 1/2) step with t_k < t1: k < (t1 - t0)/step - 1/2
     const double r = (t1 - t0) / step - 0.5;
     int kb = 0, ke = r > 0.0 ? (int)ceil(fmin(r, 2.0e9)) : 0;
+    if (J.brick) {
+        // a brick keeps the scan points inside its own box; neighbouring bricks
+        // compute the shared crossing with the same expression, so every scan
+        // point belongs to exactly one brick
+        const double bl[3] = {(double)J.org[0], (double)J.org[1], (double)J.org[2]};
+        const double bh[3] = {bl[0] + J.dims[0], bl[1] + J.dims[1], bl[2] + J.dims[2]};
+        double blo, bhi;
+        if (!slab(bl, bh, blo, bhi) || !(bhi > blo)) return false;
+        kb = max(kb, (int)ceil(fmin(fmax((blo - t0) / step - 0.5, -1.0), 2.0e9)));
+        ke = min(ke, (int)ceil(fmin(fmax((bhi - t0) / step - 0.5, -1.0), 2.0e9)));
+    }
     // each plane keeps one interval of k: n.(o + t d) + d >= 0 is affine in t.
     // Bounds in closed form; a point this can misplace lies within FP64
     // rounding of the plane, far inside the decision margin
@@ -305,6 +333,7 @@ __device__ __forceinline__ bool setup_ray(const DevJob& J, int px, int py, RaySe
     }
     R.kb = kb;
     R.ke = ke;
+    R.t_first = (float)(t0 + ((double)kb + 0.5) * step);
     return true;
 }
 
@@ -448,7 +477,8 @@ template <int INTERP>
 __device__ __forceinline__ void point_generic(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                               int k, float (&E)[3], float& S) {
     const float tk = ((float)k + 0.5f) * (float)J.step;
-    const float p[3] = {fmaf(tk, R.d[0], R.pb[0]), fmaf(tk, R.d[1], R.pb[1]), fmaf(tk, R.d[2], R.pb[2])};
+    float p[3];
+    point_at(J, R, tk, p);
     const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
     S = 0.f;
     E[0] = E[1] = E[2] = 0.f;
@@ -493,7 +523,8 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
         for (int u = 0; u < U; ++u) {
             const int kk = min(k + u, R.ke - 1);
             const float tk = ((float)kk + 0.5f) * step;
-            const float p[3] = {fmaf(tk, R.d[0], R.pb[0]), fmaf(tk, R.d[1], R.pb[1]), fmaf(tk, R.d[2], R.pb[2])};
+            float p[3];
+            point_at(J, R, tk, p);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (INTERP == 0) {
@@ -768,7 +799,53 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
             const size_t pix = (size_t)py * J.width + px;
             reinterpret_cast<float4*>(J.out)[pix] = c;
             if (J.out_samples) J.out_samples[pix] = count;
+            if (J.out_depth) J.out_depth[pix] = hit ? R.t_first : __builtin_inff();
         }
+    }
+}
+
+// Sort-last compositing of partial images: per pixel, order the layers by
+// the ray parameter of their first scan point and apply the front-to-back
+// operator (C, A) o (C', A') = (C + (1-A) C', A + (1-A) A').
+struct CompositeArgs {
+    const float4* rgba[kMaxLayers];
+    const float* depth[kMaxLayers];
+    int n;
+    int64_t n_pixels;
+    float4* out;
+};
+
+__global__ void composite_kernel(CompositeArgs a) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_pixels;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float dep[kMaxLayers];
+        int idx[kMaxLayers];
+        for (int l = 0; l < a.n; ++l) {
+            dep[l] = a.depth[l][i];
+            idx[l] = l;
+        }
+        for (int l = 1; l < a.n; ++l) {          // insertion sort, stable
+            const float dv = dep[l];
+            const int iv = idx[l];
+            int m = l - 1;
+            while (m >= 0 && dep[m] > dv) {
+                dep[m + 1] = dep[m];
+                idx[m + 1] = idx[m];
+                --m;
+            }
+            dep[m + 1] = dv;
+            idx[m + 1] = iv;
+        }
+        float Cr = 0.f, Cg = 0.f, Cb = 0.f, A = 0.f;
+        for (int l = 0; l < a.n; ++l) {
+            const float4 c = a.rgba[idx[l]][i];
+            const float T = 1.f - A;
+            Cr = fmaf(T, c.x, Cr);
+            Cg = fmaf(T, c.y, Cg);
+            Cb = fmaf(T, c.z, Cb);
+            A = fmaf(T, c.w, A);
+        }
+        a.out[i] = make_float4(Cr, Cg, Cb, A);
     }
 }
 
@@ -872,6 +949,23 @@ int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, 
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(strided_copy_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0,
+                       (hipStream_t)stream, a);
+    return hipGetLastError();
+}
+
+int launch_composite(const float* const* rgba, const float* const* depth, int n_layers, int64_t n_pixels, float* out,
+                     void* stream) {
+    CompositeArgs a;
+    for (int l = 0; l < kMaxLayers; ++l) {
+        a.rgba[l] = l < n_layers ? reinterpret_cast<const float4*>(rgba[l]) : nullptr;
+        a.depth[l] = l < n_layers ? depth[l] : nullptr;
+    }
+    a.n = n_layers;
+    a.n_pixels = n_pixels;
+    a.out = reinterpret_cast<float4*>(out);
+    if (n_pixels <= 0) return hipSuccess;
+    const int64_t blocks = (n_pixels + 255) / 256;
+    hipLaunchKernelGGL(composite_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0,
                        (hipStream_t)stream, a);
     return hipGetLastError();
 }

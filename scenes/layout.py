@@ -70,6 +70,7 @@ class SourceSpec:
     enabled: bool = True
     persistent: bool = True
     tf: List[Tuple[float, float, float, float, float]] = dataclasses.field(default_factory=list)
+    iso: float = float("nan")            # iso value in iso-surface mode (NaN: the source draws no surface)
 
     def nbytes(self) -> int:
         return int(sum(b.nbytes for b in self.buffers))
@@ -103,6 +104,7 @@ class Scene:
     ert_threshold: float = 0.999
     seed: Optional[int] = None
     label: str = ""
+    mode: str = "volume"                 # "volume" (emission-absorption) or "iso" (first iso-surface)
 
     def with_(self, **kw) -> "Scene":
         return dataclasses.replace(self, **kw)
@@ -198,13 +200,13 @@ def store_field(values: np.ndarray, dtype: str = "f32", guard: int = 1, *,
 
 def make_source(name: str, values: np.ndarray, *, dtype: str = "f32", guard: int = 1,
                 chain: str = "", weight: float = 1.0, tf=None, enabled: bool = True,
-                persistent: bool = True, **layout_kw) -> SourceSpec:
+                persistent: bool = True, iso: float = float("nan"), **layout_kw) -> SourceSpec:
     buffers, comp, strides, stored = store_field(values, dtype, guard, **layout_kw)
     if stored.ndim == 3:
         stored = stored[..., None]
     return SourceSpec(name=name, f_dim=stored.shape[3], dtype=dtype, buffers=buffers, comp=comp,
                       strides=strides, guard=guard, values=stored, chain=chain, weight=weight,
-                      enabled=enabled, persistent=persistent, tf=list(tf or []))
+                      enabled=enabled, persistent=persistent, tf=list(tf or []), iso=float(iso))
 
 
 def logical_values(src: SourceSpec) -> np.ndarray:

@@ -422,8 +422,112 @@ def pin_fp16_bf16_reads(lib):
             assert abs(a - min(val * 0.01, 1.0)) < 1e-12, (val, dt, a)
 
 
+# ---------------------------------------------------------------------------
+# iso-surface mode: affine ramp (exact crossing and normal), sphere (bound)
+# ---------------------------------------------------------------------------
+
+def _iso_ramp_scene(direction, iso, interpolation=1, width=7, height=5):
+    dims = (16, 6, 6)
+    src = make_source("ramp", fields.ramp(dims, 1, 0.0625, 0.03125, 0), guard=1,
+                      tf=[(0.0, 0.2, 0.4, 0.6, 0.1), (1.0, 1.0, 0.8, 0.0, 0.9)])
+    src.iso = iso
+    c = np.array(dims, dtype=np.float64) / 2.0
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    eye = c - 20.0 * d
+    up = (0.0, 0.0, 1.0)
+    cam = Camera(eye=tuple(eye), center=tuple(c), up=up, projection="orthographic", ortho_height=2.0)
+    sc = Scene(dims=dims, sources=[src], camera=cam, width=width, height=height, step=0.5,
+               interpolation=interpolation, ert_threshold=1.0, mode="iso")
+    return sc
+
+
+def pin_iso_plane(lib):
+    iso = 0.5                                   # 0.0625 x + 0.03125 = 0.5  ->  x* = 7.5
+    x_star = (iso - 0.03125) / 0.0625
+    tf_rgb = np.array([0.2, 0.4, 0.6]) + iso * (np.array([1.0, 0.8, 0.0]) - np.array([0.2, 0.4, 0.6]))
+    for direction, cos in (((1.0, 0.0, 0.0), 1.0), ((-1.0, 0.0, 0.0), 1.0), ((1.0, 0.0, 1.0), 2 ** -0.5)):
+        sc = _iso_ramp_scene(direction, iso)
+        rec = oracle.render(sc, lib=lib)
+        img, cnt = _img(rec, sc), _cnt(rec, sc)
+        centre = img[sc.height // 2, sc.width // 2]
+        assert centre[3] == 1.0, (direction, centre)
+        assert np.allclose(centre[:3], tf_rgb * (0.3 + 0.7 * cos), atol=1e-12), (direction, centre)
+        if direction == (1.0, 0.0, 0.0):
+            # samples at x = (k + 1/2)/2: the first at or past x* ends the ray
+            k = next(k for k in range(64) if (k + 0.5) * 0.5 >= x_star)
+            assert cnt[sc.height // 2, sc.width // 2] == k + 1
+        assert np.all(img[..., 3] == 1.0)        # every ray crosses the plane
+    # nothing crosses an iso value outside the field's range
+    sc = _iso_ramp_scene((1.0, 0.0, 0.0), 5.0)
+    assert np.all(oracle.render(sc, lib=lib)["rgba"] == 0.0)
+
+
+def pin_iso_bilinear(lib):
+    """v = a x + c x z + b is reproduced exactly by trilinear interpolation and by
+    half-voxel central differences; along a ray parallel to x at height z0 it is
+    linear, so the refined crossing x* = (iso - b) / (a + c z0) is exact, and the
+    gradient (a + c z0, 0, c x*) fixes the shading through x*."""
+    a_, c_, b_ = 0.0625, 0.015625, 0.125          # dyadic: every stored value is exact in FP32
+    dims = (16, 6, 6)
+    xs = np.arange(-1, 17) + 0.5
+    zs = np.arange(-1, 7) + 0.5
+    v = np.empty((8, 8, 18, 1))
+    v[..., 0] = (a_ * xs[None, None, :] + c_ * xs[None, None, :] * zs[:, None, None] + b_) * np.ones((8, 8, 18))
+    iso = b_ + (a_ + 3.0 * c_) * 5.1           # x* = 5.1 at z0 = 3, between the samples at 4.75 and 5.25
+    src = make_source("bilinear", v, guard=1, tf=[(0.0, 0.9, 0.5, 0.1, 0.2), (1.0, 0.1, 0.5, 0.9, 0.7)])
+    src.iso = iso
+    tf_rgb = np.array([0.9, 0.5, 0.1]) + iso * (np.array([0.1, 0.5, 0.9]) - np.array([0.9, 0.5, 0.1]))
+    for sign in (1.0, -1.0):
+        eye = (8.0 - sign * 20.0, 3.0, 3.0)
+        cam = Camera(eye=eye, center=(8.0, 3.0, 3.0), up=(0.0, 0.0, 1.0), projection="orthographic",
+                     ortho_height=3.0)
+        sc = Scene(dims=dims, sources=[src], camera=cam, width=3, height=5, step=0.5, interpolation=1,
+                   ert_threshold=1.0, mode="iso")
+        img = _img(oracle.render(sc, lib=lib), sc)
+        for j in range(sc.height):
+            for i in range(sc.width):
+                hit, o, d, t0, t1 = oracle.ray(sc, i, j, lib=lib)
+                assert hit and abs(d[0]) == 1.0
+                z0 = o[2]
+                x_star = (iso - b_) / (a_ + c_ * z0)
+                g = np.array([a_ + c_ * z0, 0.0, c_ * x_star])
+                cos = abs(g[0]) / np.linalg.norm(g)
+                assert np.allclose(img[j, i, :3], tf_rgb * (0.3 + 0.7 * cos), rtol=0, atol=1e-12), (sign, i, j)
+                assert img[j, i, 3] == 1.0
+    # a clip plane keeping x >= 6 removes the crossing from every ray
+    sc = sc.with_(clip=[(1.0, 0.0, 0.0, -6.0)])
+    assert np.all(oracle.render(sc, lib=lib)["rgba"] == 0.0)
+
+
+def pin_iso_sphere(lib):
+    """|p - c|^2 through trilinear interpolation lies in [r^2, r^2 + 3/4]: the surface radius is bounded."""
+    dims = (24, 24, 24)
+    c = np.array([12.0, 12.0, 12.0])
+    xs = np.arange(-1, 25) + 0.5
+    Z, Y, X = np.meshgrid(xs, xs, xs, indexing="ij")
+    v = np.stack([X - c[0], Y - c[1], Z - c[2]], axis=-1)
+    R = 8.0
+    src = make_source("sphere", v.astype(np.float32), guard=1, chain="pow(2) | sum",
+                      tf=configs.constant_tf((0.5, 0.5, 0.5), 1.0))
+    src.iso = R * R
+    cam = Camera(eye=(40.0, 12.0, 12.0), center=(12.0, 12.0, 12.0), up=(0.0, 0.0, 1.0), fovy_deg=30.0)
+    sc = Scene(dims=dims, sources=[src], camera=cam, width=9, height=9, step=0.25, interpolation=1,
+               ert_threshold=1.0, mode="iso")
+    rec = oracle.render(sc, lib=lib)
+    img = _img(rec, sc)
+    assert img[4, 4, 3] == 1.0                  # the centre ray meets the sphere
+    # along the centre ray (the x axis) the crossing lies between radius sqrt(R^2 - 3/4) and R
+    # and the normal is radial, so the headlight term is close to 1
+    assert img[4, 4, 0] > 0.5 * (0.3 + 0.7 * 0.99)
+    hits = img[..., 3] == 1.0
+    assert 10 <= hits.sum() <= 81
+    assert not hits[0, 0] and not hits[0, 8]     # corner rays pass beside the sphere
+
+
 ALL_PINS = [pin_constant_slab, pin_constant_slab_weight_and_two_sources, pin_mix_saturation,
             pin_constant_slab_ert, pin_constant_slab_clip, pin_linear_ramp, pin_functor_examples,
             pin_chain_render_equivalence, pin_tf_table, pin_classification_lookup, pin_geometry,
             pin_orientation, pin_perspective_symmetry, pin_brute_force, pin_ert_bound,
-            pin_fp16_bf16_reads]
+            pin_fp16_bf16_reads, pin_iso_plane, pin_iso_bilinear,
+            pin_iso_sphere]

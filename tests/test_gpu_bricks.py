@@ -1,0 +1,111 @@
+"""Sort-last rendering on one GPU: bricks on the global step grid, then over-compositing.
+
+A volume is cut into bricks, each stored with one guard layer copied from the
+global field (as neighbouring ranks would provide them, Sec. 3.1); each brick
+renders only the scan points inside its own box and writes the depth of its
+first scan point; isaac_composite orders the partial images per pixel and
+combines them front to back.  Without early termination the result must
+equal the whole-volume render up to FP32 rounding of the compositing order,
+and the oracle's whole-volume image within the parity tolerance.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.oracle import NO_TERMINATION
+from parity import compare, log
+from scenes import configs, make_source
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1611_09048_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(device=0)
+    yield c
+    c.close()
+
+
+def brick_sources(scene, lo, hi):
+    """The scene's sources restricted to cells [lo, hi) plus one guard layer from the global field."""
+    out = []
+    for s in scene.sources:
+        g = s.guard
+        assert g == 1
+        v = s.values[lo[2]:hi[2] + 2, lo[1]:hi[1] + 2, lo[0]:hi[0] + 2]   # global index i -> array i + 1
+        b = make_source(s.name, v.astype(np.float32) if s.dtype == "f32" else v, dtype=s.dtype, guard=1,
+                        chain=s.chain, weight=s.weight, tf=s.tf)
+        assert np.array_equal(b.values, v)
+        out.append(b)
+    return out
+
+
+def render_bricks(ctx, scene, cuts, ert=NO_TERMINATION):
+    import torch
+    from paper_1611_09048_amd import device
+    dims = scene.dims
+    layers, depths, vols = [], [], []
+    vid = 20
+    for i in range(len(cuts[0]) - 1):
+        for j in range(len(cuts[1]) - 1):
+            for k in range(len(cuts[2]) - 1):
+                lo = (cuts[0][i], cuts[1][j], cuts[2][k])
+                hi = (cuts[0][i + 1], cuts[1][j + 1], cuts[2][k + 1])
+                bdims = tuple(h - l for l, h in zip(lo, hi))
+                bs = scene.with_(dims=bdims, sources=brick_sources(scene, lo, hi))
+                vols.append(device.upload_volume(ctx, bs, vid))
+                img = device.new_image(scene)
+                dep = torch.full((scene.height, scene.width), float("nan"), device="cuda")
+                ctx.render([device.render_job(scene, vid, img, brick_origin=lo, global_dims=dims,
+                                              out_depth=dep.data_ptr(), ert_threshold=ert)])
+                layers.append(img)
+                depths.append(dep)
+                vid += 1
+    out = device.new_image(scene)
+    ctx.composite([l.data_ptr() for l in layers], [d.data_ptr() for d in depths], scene.width, scene.height,
+                  out.data_ptr())
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    del vols
+    return res, len(layers)
+
+
+@pytest.mark.parametrize("cuts_kind", ["halves", "uneven"])
+@pytest.mark.parametrize("direction", [configs.D0, (-0.3, 0.9, -0.5)])
+def test_bricks_composite_to_the_whole_image(ctx, cuts_kind, direction):
+    from paper_1611_09048_amd import device
+    sc = configs.pic3(n=48, width=160, height=120, direction=direction)
+    n = 48
+    cuts = ([0, 24, 48],) * 3 if cuts_kind == "halves" else ([0, 17, 48], [0, 30, 41, 48], [0, 9, 48])
+    whole, _ = device.render_scene(ctx, sc, ert_threshold=NO_TERMINATION, count=False)
+    comp, nl = render_bricks(ctx, sc, cuts)
+    log(f"bricks {cuts_kind} ({nl} layers) dir={direction}: max |composite - whole| = {np.abs(comp - whole).max():.3e}")
+    assert np.isfinite(comp).all()
+    assert np.abs(comp - whole).max() <= 1e-6
+    rec = oracle.render(sc, ert_threshold=NO_TERMINATION)
+    compare(comp.reshape(-1, 4), None, rec, label=f"composite of {nl} bricks vs oracle")
+
+
+def test_brick_depth_and_single_layer(ctx):
+    """A brick equal to the whole volume reproduces the whole render bit for bit; depth is +inf off the box."""
+    import torch
+    from paper_1611_09048_amd import device
+    sc = configs.pic3(n=32, width=90, height=70)
+    whole, cnt = device.render_scene(ctx, sc, ert_threshold=NO_TERMINATION)
+    vol = device.upload_volume(ctx, sc, 60)
+    img = device.new_image(sc)
+    dep = torch.zeros((sc.height, sc.width), device="cuda")
+    ctx.render([device.render_job(sc, 60, img, brick_origin=(0, 0, 0), global_dims=sc.dims,
+                                  out_depth=dep.data_ptr(), ert_threshold=NO_TERMINATION)])
+    torch.cuda.synchronize()
+    assert np.array_equal(img.cpu().numpy(), whole)
+    d = dep.cpu().numpy()
+    assert np.array_equal(np.isfinite(d), cnt > 0)
+    assert (cnt > 0).any() and (cnt == 0).any()
+    del vol

@@ -53,12 +53,19 @@ MUTANTS = [
     ("guard_ignored", "if (src->guard < 1) q[a] = clamp_int(", "if (src->guard < 2) q[a] = clamp_int("),
     ("disabled_read", "        if (!src->enabled) continue;                  /* never read */\n", ""),
     ("ert_strict", "if (A >= sc->ert_threshold) {", "if (A > sc->ert_threshold + 1e-3) {"),
-    ("nearest_rounds", "clamp_int((int)floor(p[a]), 0, sc->dims[a] - 1);\n            x = source_value",
-     "clamp_int((int)floor(p[a] + 0.5), 0, sc->dims[a] - 1);\n            x = source_value"),
+    ("nearest_rounds", "cell ? cell[a] : clamp_int((int)floor(p[a]), 0, sc->dims[a] - 1);",
+     "cell ? cell[a] : clamp_int((int)floor(p[a] + 0.5), 0, sc->dims[a] - 1);"),
     ("half_exponent_bias", "e - 25);", "e - 24);"),
     ("bf16_shift", "(uint32_t)b << 16;", "(uint32_t)b << 15;"),
     ("parallel_slab_open", "if (o[a] < 0.0 || o[a] > n) return 0;", "if (o[a] < 0.0) return 0;"),
     ("exit_inclusive", "int inside = t < t1;", "int inside = t <= t1 + 0.25;"),
+    ("iso_midpoint", "f = (src->iso - prev[s]) / (x[s] - prev[s]);", "f = 0.5;"),
+    ("iso_refine_from_far_end", "double ts = t_prev + f * (t - t_prev)", "double ts = t - f * (t - t_prev)"),
+    ("iso_light_swapped", "double light = 0.3 + 0.7 * cosine;", "double light = 0.7 + 0.3 * cosine;"),
+    ("iso_colour_of_sample", "classify(P->table[hit], src->iso, rgba);", "classify(P->table[hit], x[hit], rgba);"),
+    ("iso_rising_only", "((prev[s] >= src->iso) != (x[s] >= src->iso))", "(prev[s] < src->iso && x[s] >= src->iso)"),
+    ("iso_gradient_skewed", "qm[a] -= 0.5;", "qm[(a + 1) % 3] -= 0.5;"),
+    ("iso_translucent", "px->rgba[3] = 1.0;\n            break;", "px->rgba[3] = 0.5;\n            break;"),
 ]
 
 CHILD = r"""
