@@ -63,6 +63,7 @@ enum {
 typedef enum { ISAAC_F32 = 0, ISAAC_F16 = 1, ISAAC_BF16 = 2 } isaac_dtype;
 enum { ISAAC_PERSPECTIVE = 0, ISAAC_ORTHOGRAPHIC = 1 };
 enum { ISAAC_NEAREST = 0, ISAAC_TRILINEAR = 1 };
+enum { ISAAC_VOLUME = 0, ISAAC_ISO = 1 };     /* render modes */
 
 /* isaac_render flags */
 #define ISAAC_ASYNC 1u       /* enqueue on the context stream and return without waiting */
@@ -173,6 +174,20 @@ typedef struct {
     const int32_t* global_dims;       /* host, 3 ints (required with brick_origin) */
     float* out_depth;                 /* device or NULL: per pixel, ray parameter of the first scan point
                                          (+inf where there is none), the compositing order */
+    /* Render mode.  ISAAC_VOLUME: emission-absorption compositing of every
+     * source (Sec. 3.2).  ISAAC_ISO: iso-surfaces (a listed feature of Sec. 3):
+     * the same scan points; the surface is the first place where a source's
+     * interpolated, functor-transformed value crosses that source's iso
+     * value between two consecutive scan points, placed by linear
+     * interpolation between them; the pixel is opaque, coloured by the
+     * source's transfer function at the iso value times
+     * 0.3 + 0.7 |cos| of the angle between the ray and the central-difference
+     * gradient (half a voxel each side).  Weights and ert_threshold are
+     * unused; out_samples counts scan points up to and including the one
+     * after the crossing.  Not combinable with brick_origin. */
+    int32_t mode;                     /* ISAAC_VOLUME (0) or ISAAC_ISO */
+    const float* iso_values;          /* host, one per source (ISAAC_ISO); NaN: the source draws no surface
+                                         and is not read; NULL: no source draws one */
 } isaac_render_desc;
 
 /* Ray-cast jobs (all validated before any launch).  One job is one kernel

@@ -350,6 +350,13 @@ static int clamp_int(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi 
 /* The chain output of source s at integer cell (x, y, z). */
 static double source_value(const prepared* P, int s, int x, int y, int z) {
     const oracle_source* src = &P->sc->src[s];
+    const int q[3] = {x, y, z};
+    for (int a = 0; a < 3; a++)
+        if (q[a] < -src->guard || q[a] > P->sc->dims[a] - 1 + src->guard) {
+            /* cannot happen for positions inside the box; never read undeclared memory */
+            fprintf(stderr, "oracle: source %d read at index %d on axis %d, outside its guard\n", s, q[a], a);
+            abort();
+        }
     double v[4];
     for (int c = 0; c < src->f_dim; c++) v[c] = read_component(src, c, x, y, z);
     return apply_chain(&P->ch[s], v, NULL);

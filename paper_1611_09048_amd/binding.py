@@ -22,6 +22,7 @@ ERRORS = {
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 PERSPECTIVE, ORTHOGRAPHIC = 0, 1
 NEAREST, TRILINEAR = 0, 1
+VOLUME, ISO = 0, 1
 ASYNC, TIMING, NO_GRAPH = 1, 2, 4
 MAX_SOURCES, MAX_FUNCTORS, MAX_CLIP, MAX_BATCH = 8, 8, 8, 256
 
@@ -65,7 +66,8 @@ class RenderDesc(ctypes.Structure):
                 ("ert_threshold", ctypes.c_float), ("out_rgba", ctypes.c_void_p),
                 ("out_samples", ctypes.c_void_p), ("update_pointer", ctypes.c_void_p),
                 ("brick_origin", ctypes.POINTER(ctypes.c_int32)), ("global_dims", ctypes.POINTER(ctypes.c_int32)),
-                ("out_depth", ctypes.c_void_p)]
+                ("out_depth", ctypes.c_void_p), ("mode", ctypes.c_int32),
+                ("iso_values", ctypes.POINTER(ctypes.c_float))]
 
 
 EXPORTS = ["isaac_init", "isaac_destroy", "isaac_last_error", "isaac_init_error", "isaac_set_sources",
@@ -287,7 +289,7 @@ def render_desc(*, volume_id: int, width: int, height: int, eye, center, up, fov
                 projection: int = PERSPECTIVE, ortho_height: float = 0.0, step: float = 0.5,
                 interpolation: int = NEAREST, clip=(), tf_handles=None, weights=None, enabled=None,
                 ert_threshold: float = 0.0, out_rgba: int = 0, out_samples: int = 0, brick_origin=None,
-                global_dims=None, out_depth: int = 0) -> RenderDesc:
+                global_dims=None, out_depth: int = 0, mode: int = 0, iso_values=None) -> RenderDesc:
     j = RenderDesc()
     j.volume_id = volume_id
     j.width, j.height = width, height
@@ -329,5 +331,10 @@ def render_desc(*, volume_id: int, width: int, height: int, eye, center, up, fov
         j.brick_origin = a
         j.global_dims = b
     j.out_depth = out_depth or None
+    j.mode = mode
+    if iso_values is not None:
+        a = _arr(ctypes.c_float, [float(v) for v in iso_values])
+        keep.append(a)
+        j.iso_values = a
     j._keep = keep          # arrays referenced by pointer stay alive with the struct
     return j

@@ -523,6 +523,14 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
     if (!(j.ert_threshold >= 0.0f) || !std::isfinite(j.ert_threshold))
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "ert_threshold must be >= 0");
     if (need_out && !j.out_rgba) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "out_rgba is NULL");
+    if (j.mode != ISAAC_VOLUME && j.mode != ISAAC_ISO)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "unknown render mode %d", j.mode);
+    if (j.mode == ISAAC_ISO && j.brick_origin)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "iso-surface mode does not render bricks");
+    if (j.mode == ISAAC_ISO && j.iso_values)
+        for (int s = 0; s < (int)v.src.size(); ++s)
+            if (std::isinf(j.iso_values[s]))
+                return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "iso value of source %d is infinite", s);
     CameraBasis cb;
     std::string err;
     if (!camera_basis(j, cb, err)) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "%s", err.c_str());
@@ -590,7 +598,12 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
         int32_t tf = j.tf_handles ? j.tf_handles[s] : v.tf[s];
         if (tf < 0 || tf >= ctx->tf_capacity || !ctx->tf_slots[tf].live || (j.tf_handles && tf == 0))
             return set_err(ctx, ISAAC_ERR_NOT_FOUND, "transfer table handle %d of source %d is not live", tf, s);
-        if (!en || w == 0.0f) continue;   // never read: a zero weight contributes exactly nothing
+        const float iso = j.mode == ISAAC_ISO && j.iso_values ? j.iso_values[s] : NAN;
+        if (j.mode == ISAAC_ISO) {
+            if (!en || std::isnan(iso)) continue;   // draws no surface: never read
+        } else if (!en || w == 0.0f) {
+            continue;                                // never read: a zero weight contributes exactly nothing
+        }
         if (!sh.desc.comp[0] && !sh.shadow)
             return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source %d is enabled but has no data", s);
         DevSource& ds = dj.src[n_act++];
@@ -608,9 +621,17 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
         for (int o = 0; o < sh.chain.n_ops; ++o) ds.ops[o] = sh.chain.ops[o];
         ds.tf_slot = tf;
         ds.weight = w;
+        ds.iso = j.mode == ISAAC_ISO ? iso : 0.0f;
     }
     dj.n_src = n_act;
+    dj.mode = j.mode;
     dj.sig = signature_of(dj);
+    if (dj.mode == ISAAC_ISO) {
+        // iso jobs run their own one-lane kernel with the runtime source loop
+        dj.sig = SIG_GENERIC;
+        dj.waves_hint = 0;
+        set_tiles(dj, 1, 1);
+    }
     *n_active_out = n_act;
     return ISAAC_OK;
 }
@@ -707,6 +728,8 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     for (const DevJob& dj : djs)
         if (dj.sig != la.sig) la.sig = -1;
     if (la.sig == SIG_GENERIC) la.sig = -1;
+    la.mode = djs[0].mode;
+    if (la.mode == ISAAC_ISO) la.sig = -2;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (flags & ISAAC_TIMING) {
         t0 = get_event(ctx);
@@ -811,7 +834,7 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
     std::vector<std::vector<DevJob>> groups;
     std::vector<int> keys;
     for (const DevJob& dj : djs) {
-        const int key = dj.lanes * 16 + dj.unroll * 2 + dj.waves_hint;
+        const int key = dj.mode * 1024 + dj.lanes * 16 + dj.unroll * 2 + dj.waves_hint;
         size_t g = 0;
         while (g < keys.size() && keys[g] != key) ++g;
         if (g == keys.size()) {

@@ -58,7 +58,7 @@ struct DevSource {
     int32_t n_ops;
     int32_t tf_slot;       // index into the transfer-table pool
     float weight;
-    int32_t pad;
+    float iso;             // iso value (iso-surface jobs)
     DevOp ops[kMaxOps];
 };
 
@@ -89,6 +89,7 @@ struct DevJob {
     int32_t lanes;         // lanes sharing one ray (1, 2, 4, 8 or 16)
     int32_t waves_hint;    // 1: run the variant compiled for at least 4 waves per SIMD
     int32_t sig;           // Signature of the active sources
+    int32_t mode;          // 0 volume compositing, 1 first iso-surface
     int32_t tiles_x, tiles_y;
     int32_t tile_begin;    // first tile index of this job in the batch
     float* out;            // device RGBA32F image
@@ -111,6 +112,7 @@ struct LaunchArgs {
     int lanes;                 // lanes per ray (kernel variant); 1 when unroll > 1
     int waves_hint;            // 1: the variant compiled for at least 4 waves per SIMD
     int sig;                   // the jobs' common Signature, or -1 when they differ
+    int mode;                  // 1: iso-surface jobs (all jobs of a launch share the mode)
 };
 
 int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t

@@ -718,6 +718,64 @@ __device__ __forceinline__ void march_dispatch(const DevJob& J, const float4* __
     }
 }
 
+// Iso-surface mode (a listed feature, Sec. 3; the paper gives no algorithm):
+// the first place where a source's interpolated chain output crosses its iso
+// value between two consecutive scan points, placed by linear interpolation
+// between them; opaque, coloured by the source's table at the iso value and
+// lit by a headlight, 0.3 + 0.7 |cos| of the angle between the ray and the
+// central-difference gradient (half a voxel each side).  One lane per ray;
+// the source loop is uniform, so every source's buffer resource stays scalar.
+template <int INTERP>
+__device__ __forceinline__ void march_iso(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                          float4& out, int& count) {
+    const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
+    const float step = (float)J.step;
+    float prev[kMaxSources];
+    int hit = -1, n = 0, k = R.kb;
+    float f = 0.f;
+    for (; k < R.ke; ++k) {
+        float p[3];
+        point_at(J, R, ((float)k + 0.5f) * step, p);
+        ++n;
+        for (int s = 0; s < J.n_src; ++s) {
+            const DevSource& S = J.src[s];
+            const float x = sample_source<INTERP>(S, dims, p);
+            if (hit < 0 && k > R.kb && ((prev[s] >= S.iso) != (x >= S.iso))) {
+                hit = s;
+                f = (S.iso - prev[s]) / (x - prev[s]);
+            }
+            prev[s] = x;
+        }
+        if (hit >= 0) break;
+    }
+    out = make_float4(0.f, 0.f, 0.f, 0.f);
+    count = n;
+    // shade, one source at a time over the lanes whose surface it is
+    for (int s = 0; s < J.n_src; ++s) {
+        if (hit != s) continue;
+        const DevSource& S = J.src[s];
+        const float tp = ((float)(k - 1) + 0.5f) * step;
+        const float ts = fmaf(f, ((float)k + 0.5f) * step - tp, tp);
+        float q[3];
+        point_at(J, R, ts, q);
+        float g[3] = {0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int a = 0; a < 3; ++a) {           // one axis at a time keeps register use low
+            const float hx = a == 0 ? 0.5f : 0.f, hy = a == 1 ? 0.5f : 0.f, hz = a == 2 ? 0.5f : 0.f;
+            const float qp[3] = {q[0] + hx, q[1] + hy, q[2] + hz}, qm[3] = {q[0] - hx, q[1] - hy, q[2] - hz};
+            const float d = sample_source<INTERP>(S, dims, qp) - sample_source<INTERP>(S, dims, qm);
+            g[0] = a == 0 ? d : g[0];
+            g[1] = a == 1 ? d : g[1];
+            g[2] = a == 2 ? d : g[2];
+        }
+        const float gl = sqrtf(fmaf(g[0], g[0], fmaf(g[1], g[1], g[2] * g[2])));
+        const float cosine = gl > 0.f ? fabsf(fmaf(g[0], R.d[0], fmaf(g[1], R.d[1], g[2] * R.d[2]))) / gl : 1.f;
+        const float light = fmaf(0.7f, fminf(cosine, 1.f), 0.3f);
+        const float4 c = classify(s_tf + s * kTfEntries, S.iso);
+        out = make_float4(c.x * light, c.y * light, c.z * light, 1.f);
+    }
+}
+
 __device__ __forceinline__ int find_job(const DevJob* __restrict__ jobs, int n_jobs, int tile) {
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -745,7 +803,8 @@ __device__ __forceinline__ bool pixel_of(const DevJob& J, int t, int lane, int w
 // issues every load of a scan point at once; W > 0 asks for at least W
 // resident waves per SIMD and evaluates the sources one after another.
 // SIGK >= 0: the kernel runs only that source signature (every job of the
-// launch has it); SIGK < 0: it dispatches on each job's signature.
+// launch has it); SIGK = -1: it dispatches on each job's signature; SIGK = -2:
+// iso-surface jobs.
 template <int U, int G, int W, int SIGK>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, 8)))
 void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ tf_pool, int* __restrict__ cursor,
@@ -787,7 +846,10 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
         int count = 0;
         if (hit) {
-            if constexpr (SIGK < 0) {
+            if constexpr (SIGK == -2) {
+                if (J.interp) march_iso<1>(J, s_tf, R, c, count);
+                else march_iso<0>(J, s_tf, R, c, count);
+            } else if constexpr (SIGK < 0) {
                 if (J.interp) march_dispatch<1, U, G, (W > 0)>(J, s_tf, R, lane, c, count);
                 else march_dispatch<0, U, G, (W > 0)>(J, s_tf, R, lane, c, count);
             } else {
@@ -896,7 +958,8 @@ KernelFn pick_specialized(int unroll, int lanes, int hint) {
     }
 }
 
-KernelFn pick_kernel(int sig, int unroll, int lanes, int hint) {
+KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
+    if (mode == 1) return raycast_kernel<1, 1, 0, -2>;
     switch (sig) {
     case SIG_F32x1: return pick_specialized<SIG_F32x1>(unroll, lanes, hint);
     case SIG_PIC3_F32: return pick_specialized<SIG_PIC3_F32>(unroll, lanes, hint);
@@ -920,7 +983,7 @@ int launch_raycast(const LaunchArgs& a, void* stream) {
     const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfEntries * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
     if (blocks == 0) return hipSuccess;
-    const KernelFn kernel = pick_kernel(a.sig, a.unroll, a.lanes, a.waves_hint);
+    const KernelFn kernel = pick_kernel(a.mode, a.sig, a.unroll, a.lanes, a.waves_hint);
     hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlockThreads), lds, (hipStream_t)stream, a.jobs,
                        reinterpret_cast<const float4*>(a.tf_pool), a.cursor, a.n_jobs, a.total_tiles, a.persistent);
     return hipGetLastError();

@@ -63,6 +63,8 @@ def render_job(scene, volume_id: int, out: torch.Tensor, samples: Optional[torch
               ortho_height=cam.ortho_height, step=scene.step, interpolation=scene.interpolation, clip=scene.clip,
               ert_threshold=float(scene.ert_threshold), out_rgba=out.data_ptr(),
               out_samples=samples.data_ptr() if samples is not None else 0)
+    if scene.mode == "iso":
+        kw.update(mode=binding.ISO, iso_values=[s.iso for s in scene.sources])
     kw.update(overrides)
     return binding.render_desc(**kw)
 

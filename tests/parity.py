@@ -2,7 +2,7 @@
 
 Tolerance: every channel of every pixel within 2e-3 of the oracle, plus the
 oracle's per-pixel allowance for decisions (nearest cell, clip plane, box
-exit, termination threshold) taken within the decision margin, where both
+exit, termination threshold, iso crossing) taken within the decision margin, where both
 outcomes are correct.  Sample counts must match exactly wherever the oracle
 flagged no such decision.
 """
@@ -13,7 +13,7 @@ import sys
 
 import numpy as np
 
-from oracle.oracle import FLAG_ERT, FLAG_NEAREST
+from oracle.oracle import FLAG_ERT, FLAG_ISO, FLAG_NEAREST
 
 TOL = 2e-3
 
@@ -44,10 +44,10 @@ def compare(gpu_rgba: np.ndarray, gpu_cnt, rec: np.ndarray, tol: float = TOL, la
                     int(rec["samples"][i]), (int(gpu_cnt[i]) if gpu_cnt is not None else None)) for i in idx]
         raise AssertionError(f"{label}: {int(bad.any(axis=1).sum())} pixels outside tolerance; first: {details}")
     if check_counts and gpu_cnt is not None:
-        # counts move only with clip-plane and box-exit decisions, unless a nearest-cell or
-        # termination decision changed when the ray stops
+        # counts move only with clip-plane and box-exit decisions, unless a nearest-cell,
+        # termination or iso-crossing decision changed where the ray stops
         c = np.asarray(gpu_cnt).reshape(-1).astype(np.int64)
-        free = (rec["kinds"] & (FLAG_NEAREST | FLAG_ERT)) != 0
+        free = (rec["kinds"] & (FLAG_NEAREST | FLAG_ERT | FLAG_ISO)) != 0
         mism = (np.abs(c - rec["samples"]) > rec["count_slack"]) & ~free
         assert not mism.any(), (f"{label}: sample counts differ at {int(mism.sum())} pixels, e.g. "
                                 f"{[(int(i), int(c[i]), int(rec['samples'][i])) for i in np.argwhere(mism)[:5, 0]]}")

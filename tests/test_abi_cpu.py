@@ -55,7 +55,8 @@ int main(void) {
   P(isaac_source_desc, weight) P(isaac_source_desc, update) P(isaac_source_desc, user)
   P(isaac_render_desc, eye) P(isaac_render_desc, step) P(isaac_render_desc, clip)
   P(isaac_render_desc, ert_threshold) P(isaac_render_desc, out_rgba) P(isaac_render_desc, update_pointer)
-  P(isaac_render_desc, brick_origin) P(isaac_render_desc, out_depth)
+  P(isaac_render_desc, brick_origin) P(isaac_render_desc, out_depth) P(isaac_render_desc, mode)
+  P(isaac_render_desc, iso_values)
   P(isaac_init_desc, mem_budget_bytes)
   return 0;
 }
