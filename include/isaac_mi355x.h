@@ -205,6 +205,19 @@ isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int
 isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const float* const* depth, int n_layers,
                              int width, int height, float* out, unsigned flags);
 
+/* Frame encode (the step after compositing, where the root rank compresses
+ * the image before sending it, Sec. 3.4): each pixel of a premultiplied
+ * RGBA32F image (device, width*height*4 floats) is quantized to 8 bits per
+ * channel into out (device, width*height*4 bytes, row 0 on top):
+ *   background == NULL: (q(C_r), q(C_g), q(C_b), q(A)), still premultiplied;
+ *   background = host rgb in [0,1]: (q(C_c + (1-A) bg_c), ..., 255), the
+ *     image over an opaque background;
+ * with q(v) = floor(clamp(v, 0, 1) * 255 + 1/2) and NaN -> 0, every step a
+ * separately rounded FP32 operation.  Runs on the context stream; without
+ * ISAAC_ASYNC it waits for the result. */
+isaac_status isaac_encode_rgba8(isaac_context* ctx, const float* rgba, int width, int height,
+                                const float* background, unsigned char* out, unsigned flags);
+
 /* Sum and count of the kernel durations of ISAAC_TIMING renders since the
  * last call (waits for them), then resets. */
 isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count);
@@ -252,6 +265,12 @@ isaac_status isaac_poll(isaac_context* ctx, uint64_t ticket, int* done, const fl
 /* Copy a ticket's image (waiting for it) into host memory of height*width*4
  * floats. */
 isaac_status isaac_read_image(isaac_context* ctx, uint64_t ticket, float* host_rgba);
+
+/* Encode a ticket's image as isaac_encode_rgba8 does (waiting for it) and copy
+ * the height*width*4 bytes into host memory: a quarter of the RGBA32F copy.
+ * background: host rgb in [0,1] or NULL. */
+isaac_status isaac_read_image_rgba8(isaac_context* ctx, uint64_t ticket, const float* background,
+                                    unsigned char* host_rgba8);
 
 /* Return the image memory of a completed (or not yet complete: waits) ticket. */
 isaac_status isaac_release(isaac_context* ctx, uint64_t ticket);

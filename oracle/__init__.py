@@ -15,4 +15,4 @@ early-termination threshold) can be checked against a value the paper prints;
 they are pinned by closed forms and brute force in tests/.
 """
 
-from .oracle import build, load, render, render_pixels, chain_eval, tf_table, ray  # noqa: F401
+from .oracle import build, load, render, render_pixels, chain_eval, tf_table, ray, encode_rgba8  # noqa: F401

@@ -681,3 +681,33 @@ int oracle_render_list(const oracle_scene* sc, const int32_t* px, int64_t n, ora
     free(P);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* frame encode: FP32, one rounding per operation (no contraction)      */
+/* ------------------------------------------------------------------ */
+static unsigned char quantize_channel(float v) {
+    float c;
+    if (isnan(v) || v <= 0.0f) c = 0.0f;
+    else if (v >= 1.0f) c = 1.0f;
+    else c = v;
+    float scaled = c * 255.0f;
+    float shifted = scaled + 0.5f;
+    return (unsigned char)floorf(shifted);
+}
+
+void oracle_encode_rgba8(const float* rgba, int64_t n_pixels, const float* background, unsigned char* out) {
+    for (int64_t i = 0; i < n_pixels; i++) {
+        const float* px = rgba + 4 * i;
+        unsigned char* q = out + 4 * i;
+        if (background) {
+            float transmit = 1.0f - px[3];
+            for (int c = 0; c < 3; c++) {
+                float behind = transmit * background[c];
+                q[c] = quantize_channel(px[c] + behind);
+            }
+            q[3] = 255;
+        } else {
+            for (int c = 0; c < 4; c++) q[c] = quantize_channel(px[c]);
+        }
+    }
+}

@@ -96,6 +96,13 @@ int oracle_tf_table(int n_tf, const double* tf, double* table, char* err, int er
 
 /* Ray of pixel (i, j): origin, unit direction and the box interval [t0, t1]
  * (t0 >= 0); returns 1 if the ray meets the box, 0 otherwise. */
+/* Frame encode (the image is compressed before it is sent, Sec. 3.4): each
+ * premultiplied RGBA pixel, optionally over an opaque rgb background, is
+ * quantized to 8 bits, q(v) = floor(clamp(v,0,1)*255 + 1/2), NaN -> 0.  The
+ * quantization is an integer decision, taken here in FP32 with every
+ * operation rounded separately (the precision of the library's output). */
+void oracle_encode_rgba8(const float* rgba, int64_t n_pixels, const float* background, unsigned char* out);
+
 int oracle_ray(const oracle_scene* sc, int i, int j, double o[3], double d[3],
                double* t0, double* t1);
 

@@ -78,6 +78,9 @@ def _declare(lib):
     lib.oracle_ray.argtypes = [ctypes.POINTER(_Scene), ctypes.c_int, ctypes.c_int,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_encode_rgba8.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_ubyte)]
+    lib.oracle_encode_rgba8.restype = None
     for f in ("oracle_render_range", "oracle_render_list", "oracle_chain_eval", "oracle_tf_table",
               "oracle_ray"):
         getattr(lib, f).restype = ctypes.c_int
@@ -231,6 +234,20 @@ def tf_table(points, lib=None) -> np.ndarray:
     _check(lib.oracle_tf_table(len(points), pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), err, 256), err)
     return table.reshape(256, 4)
+
+
+def encode_rgba8(rgba, background=None, lib=None) -> np.ndarray:
+    """uint8 (..., 4) frame of a float32 premultiplied RGBA image (..., 4)."""
+    lib = lib or load()
+    a = np.ascontiguousarray(np.asarray(rgba, dtype=np.float32))
+    assert a.shape[-1] == 4
+    out = np.zeros(a.shape, dtype=np.uint8)
+    bg = None
+    if background is not None:
+        bg = (ctypes.c_float * 3)(*[float(np.float32(v)) for v in background])
+    lib.oracle_encode_rgba8(a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.c_int64(a.size // 4), bg,
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    return out
 
 
 def ray(scene, i: int, j: int, lib=None):

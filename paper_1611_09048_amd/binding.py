@@ -71,9 +71,10 @@ class RenderDesc(ctypes.Structure):
 
 
 EXPORTS = ["isaac_init", "isaac_destroy", "isaac_last_error", "isaac_init_error", "isaac_set_sources",
-           "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_composite", "isaac_timing",
-           "isaac_set_tile_shape", "isaac_get_tile_shape", "isaac_submit", "isaac_submit_batch", "isaac_poll",
-           "isaac_release", "isaac_read_image", "isaac_serving_usage", "isaac_check_functor_chain", "isaac_version"]
+           "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_composite", "isaac_encode_rgba8",
+           "isaac_timing", "isaac_set_tile_shape", "isaac_get_tile_shape", "isaac_submit", "isaac_submit_batch",
+           "isaac_poll", "isaac_release", "isaac_read_image", "isaac_read_image_rgba8", "isaac_serving_usage",
+           "isaac_check_functor_chain", "isaac_version"]
 
 _lib = None
 
@@ -105,6 +106,9 @@ def load(path: Optional[str] = None):
     lib.isaac_timing.argtypes = [c_ctx, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.isaac_composite.argtypes = [c_ctx, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint]
+    lib.isaac_encode_rgba8.argtypes = [c_ctx, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_uint]
+    lib.isaac_read_image_rgba8.argtypes = [c_ctx, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
     lib.isaac_set_tile_shape.argtypes = [c_ctx] + [ctypes.c_int] * 6
     lib.isaac_get_tile_shape.argtypes = [c_ctx, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 5
     lib.isaac_submit.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.POINTER(ctypes.c_uint64)]
@@ -209,6 +213,11 @@ class Context:
         d = (ctypes.c_void_p * n)(*depth_ptrs)
         self._check(self.lib.isaac_composite(self.h, r, d, n, width, height, out_ptr, flags))
 
+    def encode_rgba8(self, rgba_ptr: int, width: int, height: int, out_ptr: int, background=None, flags: int = 0):
+        """Quantize a device RGBA32F image to device RGBA8 (optionally over an opaque rgb background)."""
+        bg = (ctypes.c_float * 3)(*map(float, background)) if background is not None else None
+        self._check(self.lib.isaac_encode_rgba8(self.h, rgba_ptr, width, height, bg, out_ptr, flags))
+
     def timing(self):
         ms, n = ctypes.c_double(), ctypes.c_int()
         self._check(self.lib.isaac_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
@@ -249,6 +258,12 @@ class Context:
     def read_image(self, ticket: int, out):
         """Copy a ticket's image into the float32 numpy array `out` (height, width, 4)."""
         self._check(self.lib.isaac_read_image(self.h, ctypes.c_uint64(ticket), out.ctypes.data))
+        return out
+
+    def read_image_rgba8(self, ticket: int, out, background=None):
+        """Encode a ticket's image to RGBA8 on the device and copy it into the uint8 array `out` (h, w, 4)."""
+        bg = (ctypes.c_float * 3)(*map(float, background)) if background is not None else None
+        self._check(self.lib.isaac_read_image_rgba8(self.h, ctypes.c_uint64(ticket), bg, out.ctypes.data))
         return out
 
     def serving_usage(self):

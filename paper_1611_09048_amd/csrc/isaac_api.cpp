@@ -280,6 +280,8 @@ struct isaac_context {
     std::multimap<size_t, float*> image_cache;
     size_t cached = 0;
     uint64_t next_ticket = 1;
+    void* enc_buf = nullptr;           // RGBA8 staging of isaac_read_image_rgba8
+    size_t enc_bytes = 0;
     TileShape shapes[16];
     std::string last_error;
     bool sticky = false;
@@ -983,6 +985,7 @@ void isaac_destroy(isaac_context* ctx) {
     }
     for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
     if (ctx->tf_pool) hipFree(ctx->tf_pool);
+    if (ctx->enc_buf) hipFree(ctx->enc_buf);
     for (hipStream_t s : ctx->serve_streams) hipStreamDestroy(s);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
@@ -1120,6 +1123,22 @@ isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const
         if (!rgba[l] || !depth[l]) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "layer %d has a NULL pointer", l);
     int rc = launch_composite(rgba, depth, n_layers, (int64_t)width * height, out, ctx->stream);
     if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "composite launch: %s", hipGetErrorString((hipError_t)rc));
+    if (!(flags & ISAAC_ASYNC)) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return ISAAC_OK;
+}
+
+isaac_status isaac_encode_rgba8(isaac_context* ctx, const float* rgba, int width, int height, const float* background,
+                                unsigned char* out, unsigned flags) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!rgba || !out || width < 1 || height < 1)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "encode needs an image, an output and a size");
+    if (background)
+        for (int c = 0; c < 3; ++c)
+            if (!(background[c] >= 0.f && background[c] <= 1.f))
+                return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "background channel %d must lie in [0,1]", c);
+    int rc = launch_encode_rgba8(rgba, (int64_t)width * height, background, out, ctx->stream);
+    if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "encode launch: %s", hipGetErrorString((hipError_t)rc));
     if (!(flags & ISAAC_ASYNC)) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return ISAAC_OK;
 }
@@ -1295,6 +1314,36 @@ isaac_status isaac_read_image(isaac_context* ctx, uint64_t ticket, float* host_r
     HIP_TRY(ctx, hipEventSynchronize(t.ev));
     t.done = true;
     HIP_TRY(ctx, hipMemcpy(host_rgba, t.out, t.bytes, hipMemcpyDeviceToHost));
+    return ISAAC_OK;
+}
+
+isaac_status isaac_read_image_rgba8(isaac_context* ctx, uint64_t ticket, const float* background,
+                                    unsigned char* host_rgba8) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) return set_err(ctx, ISAAC_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!host_rgba8) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "host_rgba8 is NULL");
+    if (background)
+        for (int c = 0; c < 3; ++c)
+            if (!(background[c] >= 0.f && background[c] <= 1.f))
+                return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "background channel %d must lie in [0,1]", c);
+    Ticket& t = it->second;
+    const int64_t n = (int64_t)(t.bytes / 16);
+    if ((size_t)n * 4 > ctx->enc_bytes) {
+        if (ctx->enc_buf) HIP_TRY(ctx, hipFree(ctx->enc_buf));
+        ctx->enc_buf = nullptr;
+        ctx->enc_bytes = 0;
+        HIP_TRY(ctx, hipMalloc(&ctx->enc_buf, (size_t)n * 4));
+        ctx->enc_bytes = (size_t)n * 4;
+    }
+    // encode after the render on the context stream, then copy 4 bytes per pixel
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, t.ev, 0));
+    int rc = launch_encode_rgba8(t.out, n, background, static_cast<unsigned char*>(ctx->enc_buf), ctx->stream);
+    if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "encode launch: %s", hipGetErrorString((hipError_t)rc));
+    HIP_TRY(ctx, hipMemcpyAsync(host_rgba8, ctx->enc_buf, (size_t)n * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    t.done = true;
     return ISAAC_OK;
 }
 

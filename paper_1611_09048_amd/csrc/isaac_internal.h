@@ -124,5 +124,6 @@ int raycast_occupancy(int* blocks_per_cu);
 constexpr int kMaxLayers = 16;
 int launch_composite(const float* const* rgba, const float* const* depth, int n_layers, int64_t n_pixels,
                      float* out, void* stream);
+int launch_encode_rgba8(const float* rgba, int64_t n_pixels, const float* bg, unsigned char* out, void* stream);
 
 }  // namespace isaac

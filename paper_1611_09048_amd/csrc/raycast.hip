@@ -18,6 +18,8 @@
 // Transfer tables (256 x RGBA32F per source) live in LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "isaac_internal.h"
 
 namespace isaac {
@@ -911,6 +913,46 @@ __global__ void composite_kernel(CompositeArgs a) {
     }
 }
 
+// Frame encode: premultiplied RGBA32F over an opaque background, quantized
+// to 8 bits per channel, q = floor(clamp(v, 0, 1) * 255 + 1/2) with NaN -> 0.
+// Every operation is a separately rounded FP32 operation (no contraction), so
+// the integer codes are a fixed function of the input bits.
+struct EncodeArgs {
+    const float4* in;
+    uchar4* out;
+    int64_t n_pixels;
+    float bg[3];
+    int has_bg;
+};
+
+__device__ __forceinline__ unsigned char quantize8(float v) {
+#pragma clang fp contract(off)
+    const float c = v > 0.f ? fminf(v, 1.f) : 0.f;    // NaN -> 0
+    return (unsigned char)(int)floorf(c * 255.f + 0.5f);
+}
+
+__global__ void encode_rgba8_kernel(EncodeArgs a) {
+#pragma clang fp contract(off)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_pixels;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 c = a.in[i];
+        uchar4 q;
+        if (a.has_bg) {
+            const float t = 1.f - c.w;
+            q.x = quantize8(c.x + t * a.bg[0]);
+            q.y = quantize8(c.y + t * a.bg[1]);
+            q.z = quantize8(c.z + t * a.bg[2]);
+            q.w = 255;
+        } else {
+            q.x = quantize8(c.x);
+            q.y = quantize8(c.y);
+            q.z = quantize8(c.z);
+            q.w = quantize8(c.w);
+        }
+        a.out[i] = q;
+    }
+}
+
 __global__ void reset_counter_kernel(int* c) {
     if (threadIdx.x == 0) c[0] = 0;
 }
@@ -1030,6 +1072,19 @@ int launch_composite(const float* const* rgba, const float* const* depth, int n_
     const int64_t blocks = (n_pixels + 255) / 256;
     hipLaunchKernelGGL(composite_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0,
                        (hipStream_t)stream, a);
+    return hipGetLastError();
+}
+
+int launch_encode_rgba8(const float* rgba, int64_t n_pixels, const float* bg, unsigned char* out, void* stream) {
+    EncodeArgs a;
+    a.in = reinterpret_cast<const float4*>(rgba);
+    a.out = reinterpret_cast<uchar4*>(out);
+    a.n_pixels = n_pixels;
+    a.has_bg = bg != nullptr;
+    for (int c = 0; c < 3; ++c) a.bg[c] = bg ? bg[c] : 0.f;
+    const int64_t blocks = std::min<int64_t>((n_pixels + 255) / 256, 8192);
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(encode_rgba8_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
     return hipGetLastError();
 }
 

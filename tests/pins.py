@@ -525,9 +525,44 @@ def pin_iso_sphere(lib):
     assert not hits[0, 0] and not hits[0, 8]     # corner rays pass beside the sphere
 
 
+# ---------------------------------------------------------------------------
+# frame encode: 8-bit quantization of the premultiplied image
+# ---------------------------------------------------------------------------
+
+def pin_encode_rgba8(lib):
+    from fractions import Fraction
+    # every code k is reached exactly at k/255 (rounded to FP32), 0 and 1 at the ends
+    k = np.arange(256)
+    v = (k / 255.0).astype(np.float32)
+    img = np.stack([v, v, v, v], axis=-1)
+    q = oracle.encode_rgba8(img, lib=lib)
+    assert np.array_equal(q[:, 0], k.astype(np.uint8)) and np.array_equal(q[:, 3], k.astype(np.uint8))
+    # out of range and NaN
+    odd = np.array([[-1.0, np.nan, 2.0, np.inf], [-np.inf, -0.0, 1e-30, 0.99999994]], dtype=np.float32)
+    assert oracle.encode_rgba8(odd, lib=lib).tolist() == [[0, 0, 255, 255], [0, 0, 0, 255]]
+    # against exact rational rounding: |q - 255 v| <= 1/2, equality allowed only at a tie of the exact value
+    rng = np.random.default_rng(5)
+    r = rng.random((4000, 4), dtype=np.float32)
+    qr = oracle.encode_rgba8(r, lib=lib).astype(np.int64)
+    for x, qq in zip(r.reshape(-1)[:2000], qr.reshape(-1)[:2000]):
+        exact = Fraction(float(x)) * 255
+        assert abs(Fraction(int(qq)) - exact) <= Fraction(1, 2) + Fraction(1, 1 << 16), (x, qq)
+    # monotone in the value
+    srt = np.sort(r.reshape(-1))
+    qs = oracle.encode_rgba8(np.repeat(srt[:, None], 4, axis=1), lib=lib)[:, 0].astype(int)
+    assert np.all(np.diff(qs) >= 0)
+    # over a background: an opaque pixel ignores it, a transparent black one shows it, alpha is 255
+    bg = (0.25, 0.5, 1.0)
+    px = np.array([[0.2, 0.4, 0.6, 1.0], [0.0, 0.0, 0.0, 0.0], [0.1, 0.1, 0.1, 0.5]], dtype=np.float32)
+    qb = oracle.encode_rgba8(px, bg, lib=lib)
+    assert qb[0].tolist() == [51, 102, 153, 255]
+    assert qb[1].tolist() == [64, 128, 255, 255]
+    assert qb[2].tolist() == [int(np.floor((0.1 + 0.5 * b) * 255 + 0.5)) for b in bg] + [255]
+
+
 ALL_PINS = [pin_constant_slab, pin_constant_slab_weight_and_two_sources, pin_mix_saturation,
             pin_constant_slab_ert, pin_constant_slab_clip, pin_linear_ramp, pin_functor_examples,
             pin_chain_render_equivalence, pin_tf_table, pin_classification_lookup, pin_geometry,
             pin_orientation, pin_perspective_symmetry, pin_brute_force, pin_ert_bound,
             pin_fp16_bf16_reads, pin_iso_plane, pin_iso_bilinear,
-            pin_iso_sphere]
+            pin_iso_sphere, pin_encode_rgba8]

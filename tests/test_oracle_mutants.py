@@ -65,6 +65,10 @@ MUTANTS = [
     ("iso_colour_of_sample", "classify(P->table[hit], src->iso, rgba);", "classify(P->table[hit], x[hit], rgba);"),
     ("iso_rising_only", "((prev[s] >= src->iso) != (x[s] >= src->iso))", "(prev[s] < src->iso && x[s] >= src->iso)"),
     ("iso_gradient_skewed", "qm[a] -= 0.5;", "qm[(a + 1) % 3] -= 0.5;"),
+    ("encode_truncates", "float shifted = scaled + 0.5f;", "float shifted = scaled;"),
+    ("encode_scale_256", "float scaled = c * 255.0f;", "float scaled = c * 256.0f;"),
+    ("encode_alpha_as_transmittance", "float transmit = 1.0f - px[3];", "float transmit = px[3];"),
+    ("encode_alpha_kept_over_bg", "q[3] = 255;", "q[3] = quantize_channel(px[3]);"),
     ("iso_translucent", "px->rgba[3] = 1.0;\n            break;", "px->rgba[3] = 0.5;\n            break;"),
 ]
 
