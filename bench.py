@@ -12,9 +12,11 @@ view; steps cycle through the 26 views).  Sources are resident in device
 memory before timing starts; `value` counts the scan points composited
 (counted once per view by the kernel's counting variant, untimed).
 
-Also reported (not the headline): the same scene with FP16 and BF16 storage,
-the 64-sub-volume batch in one persistent hipGraph launch, and a short run of
-the continuous-batching server on a resident 512x512x256 volume.
+Also reported (not the headline): the same scene with FP16 and BF16 storage
+and in iso-surface mode, the RGBA8 frame encode, a field simulation on
+128^3 rendered in situ every step and every 10th step, the 64-sub-volume
+batch in one persistent hipGraph launch, and a short run of the
+continuous-batching server on a resident 512x512x256 volume.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -230,6 +232,90 @@ def serving(ctx, duration: float, rate: float, n: int = 512, depth: int = 256):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
 
+def iso_frames(ctx, n: int, width: int, height: int, steps: int = 26):
+    """The headline scene in iso-surface mode: density surface at 1.0, |E| surface at 0.2."""
+    import dataclasses
+    import torch
+    from paper_1611_09048_amd import ASYNC, TIMING, device
+    from scenes import configs
+    sc = configs.pic3(n=n, width=width, height=height)
+    sc = sc.with_(mode="iso", sources=[dataclasses.replace(s, iso=v) for s, v in
+                                       zip(sc.sources, (1.0, 0.2, float("nan")))])
+    vol = device.upload_volume(ctx, sc, 220)
+    img, cnt = device.new_image(sc), device.new_counts(sc)
+    views = [sc.with_(camera=configs.orbit_camera(sc.dims, v)) for v in configs.views26()]
+    samples, surf = [], []
+    for v in views:
+        ctx.render([device.render_job(v, 220, img, cnt)])
+        samples.append(int(cnt.to(torch.int64).sum().item()))
+        surf.append(float((img[..., 3] == 1.0).float().mean().item()))
+    jobs = [device.render_job(v, 220, img) for v in views]
+    ctx.render(jobs[:1])
+    torch.cuda.synchronize()
+    ctx.timing()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ctx.render([jobs[k % 26]], ASYNC | TIMING)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, nk = ctx.timing()
+    total = sum(samples[k % 26] for k in range(steps))
+    res = dict(gsamples_per_s=round(total / el / 1e9, 3), fps=round(steps / el, 2),
+               kernel_ms=round(ms / max(nk, 1), 4), samples_per_frame=int(np.mean(samples)),
+               surface_pixel_fraction=round(float(np.mean(surf)), 4))
+    log(f"bench: iso {res}")
+    del vol
+    return res
+
+
+def encode(ctx, width: int, height: int, reps: int = 50):
+    """RGBA32F -> RGBA8 frame encode over a background; bytes = 16 read + 4 written per pixel."""
+    import torch
+    img = torch.rand((height, width, 4), device="cuda")
+    out = torch.empty((height, width, 4), dtype=torch.uint8, device="cuda")
+    ctx.encode_rgba8(img.data_ptr(), width, height, out.data_ptr(), (1.0, 1.0, 1.0))
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    a.record(stream)
+    for _ in range(reps):
+        ctx.encode_rgba8(img.data_ptr(), width, height, out.data_ptr(), (1.0, 1.0, 1.0), 1)
+    b.record(stream)
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) * 1e3 / reps
+    res = dict(us_per_frame=round(us, 2), gb_per_s=round(width * height * 20 / (us * 1e-6) / 1e9, 1))
+    log(f"bench: encode {res}")
+    return res
+
+
+def insitu_run(ctx, n: int, width: int, height: int, steps: int = 40):
+    """A field simulation on the same stream, rendered every n-th step (zero-copy sources)."""
+    import torch
+    from paper_1611_09048_amd import binding, insitu
+    from scenes import configs
+    sim = insitu.FieldSimulation(n=n, seed=7)
+    r = insitu.InSituRenderer(ctx, sim, volume_id=230)
+    img = torch.empty((height, width, 4), device="cuda")
+    views = configs.views26()
+    dims = (n, n, n)
+
+    def make_desc(frame):
+        cam = configs.orbit_camera(dims, views[frame % 26])
+        return binding.render_desc(volume_id=230, width=width, height=height, eye=cam.eye, center=cam.center,
+                                   up=cam.up, fovy_deg=cam.fovy_deg, step=0.5, interpolation=binding.TRILINEAR,
+                                   out_rgba=img.data_ptr())
+
+    r.render(make_desc(0))
+    alone = r.run(steps, 0, make_desc)
+    res = dict(grid=n, width=width, height=height, steps=steps, sim_ms_per_step=round(alone.total_s * 1e3 / steps, 3))
+    for every in (1, 10):
+        st = r.run(steps, every, make_desc)
+        res[f"every_{every}"] = dict(frames=st.frames, ms_per_step=round(st.total_s * 1e3 / steps, 3),
+                                     render_ms_per_frame=round(st.render_s * 1e3 / max(st.frames, 1), 3),
+                                     render_share=round(st.overhead, 4))
+    log(f"bench: in situ {res}")
+    return res
+
+
 def copy_probe(ctx_unused, mib: int = 512, reps: int = 3):
     """A plain device copy of known size, for normalizing rocprof byte counters."""
     import torch
@@ -305,6 +391,9 @@ def main():
             f2 = frames(ctx, s2, max(26, args.steps // 2), 3, f" {dt}")
             extras[dt] = dict(gsamples_per_s=round(f2["gsps"], 3), kernel_ms=round(f2["kernel_ms"], 4),
                               fps=round(max(26, args.steps // 2) / f2["elapsed"], 2), tile_shape=list(f2["shape"]))
+        extras["iso"] = iso_frames(ctx, args.n, args.width, args.height)
+        extras["encode_rgba8"] = encode(ctx, args.width, args.height)
+        extras["insitu"] = insitu_run(ctx, 128, args.width, args.height)
         extras["batch64"] = batch64(ctx, 10)
         extras["serving"] = serving(ctx, args.serve_seconds, 200.0)
         extras["serving_stress"] = serving(ctx, max(2.0, args.serve_seconds / 2), 2000.0)
