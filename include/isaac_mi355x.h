@@ -69,6 +69,8 @@ enum { ISAAC_VOLUME = 0, ISAAC_ISO = 1 };     /* render modes */
 #define ISAAC_ASYNC 1u       /* enqueue on the context stream and return without waiting */
 #define ISAAC_TIMING 2u      /* bracket the ray-casting kernel with HIP events (isaac_timing) */
 #define ISAAC_NO_GRAPH 4u    /* batched renders: launch directly instead of replaying a hipGraph */
+#define ISAAC_DIRECT 8u      /* read and transform the sources inside the ray loop (no derived volume) */
+#define ISAAC_DERIVE 16u     /* use a derived volume whenever the sources allow it (no cost estimate) */
 
 typedef struct isaac_context isaac_context;   /* opaque */
 
@@ -193,7 +195,15 @@ typedef struct {
 /* Ray-cast jobs (all validated before any launch).  One job is one kernel
  * launch over its image; several jobs form one persistent launch over a
  * shared tile queue, replayed as a hipGraph unless ISAAC_NO_GRAPH.  Without
- * ISAAC_ASYNC the call returns after the images are complete. */
+ * ISAAC_ASYNC the call returns after the images are complete.
+ * Derived volume: when the call's expected scan points on a volume (8 voxel
+ * visits each under trilinear interpolation) exceed 4 per voxel, or with
+ * ISAAC_DERIVE, and at most 4 of its sources are active, the call first
+ * evaluates every active source's functor chain once per voxel (guards
+ * included) into a library-owned FP32 buffer of 4 bytes per voxel and source,
+ * kept per volume until it is redefined, and the ray loop reads that buffer.
+ * The image is the same bit for bit.  ISAAC_DIRECT never derives.  Serving
+ * calls (isaac_submit*) never derive. */
 isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags);
 
 /* Sort-last compositing (Sec. 3.1, Fig. "whole concept"): per pixel, order the

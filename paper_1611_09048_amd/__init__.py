@@ -6,8 +6,8 @@ include/isaac_mi355x.h); `binding` marshals Python arguments onto it and
 no CPU fallback: calls fail if the library is not built.
 """
 
-from .binding import (ASYNC, NEAREST, NO_GRAPH, ORTHOGRAPHIC, PERSPECTIVE, TIMING, TRILINEAR, Context, IsaacError,
-                      check_functor_chain, load, render_desc, source_desc)
+from .binding import (ASYNC, DERIVE, DIRECT, ISO, NEAREST, NO_GRAPH, ORTHOGRAPHIC, PERSPECTIVE, TIMING, TRILINEAR,
+                      VOLUME, Context, IsaacError, check_functor_chain, load, render_desc, source_desc)
 
-__all__ = ["ASYNC", "NEAREST", "NO_GRAPH", "ORTHOGRAPHIC", "PERSPECTIVE", "TIMING", "TRILINEAR", "Context",
-           "IsaacError", "check_functor_chain", "load", "render_desc", "source_desc"]
+__all__ = ["ASYNC", "DERIVE", "DIRECT", "ISO", "NEAREST", "NO_GRAPH", "ORTHOGRAPHIC", "PERSPECTIVE", "TIMING",
+           "TRILINEAR", "VOLUME", "Context", "IsaacError", "check_functor_chain", "load", "render_desc", "source_desc"]

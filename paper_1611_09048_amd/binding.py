@@ -23,7 +23,7 @@ DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 PERSPECTIVE, ORTHOGRAPHIC = 0, 1
 NEAREST, TRILINEAR = 0, 1
 VOLUME, ISO = 0, 1
-ASYNC, TIMING, NO_GRAPH = 1, 2, 4
+ASYNC, TIMING, NO_GRAPH, DIRECT, DERIVE = 1, 2, 4, 8, 16
 MAX_SOURCES, MAX_FUNCTORS, MAX_CLIP, MAX_BATCH = 8, 8, 8, 256
 
 

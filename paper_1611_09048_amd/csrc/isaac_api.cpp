@@ -211,6 +211,9 @@ struct Volume {
     int32_t dims[3] = {0, 0, 0};
     std::vector<SourceHost> src;
     std::vector<int32_t> tf;        // current table handle per source
+    // derived volume (chain outputs per voxel), rebuilt by each render call that uses it
+    void* derived = nullptr;
+    size_t derived_bytes = 0;
 };
 
 struct TfSlot {
@@ -460,6 +463,17 @@ bool camera_basis(const isaac_render_desc& j, CameraBasis& cb, std::string& err)
 
 // Which compile-time specialized loop (if any) fits the job's active sources.
 int32_t signature_of(const DevJob& dj) {
+    if (dj.n_src == 3) {
+        // three FP32 scalars interleaved in one buffer (a derived volume)
+        const DevSource* d = dj.src;
+        bool il = true;
+        for (int s = 0; s < 3; ++s)
+            il = il && d[s].f_dim == 1 && d[s].dtype == DT_F32 && d[s].n_ops == 0 && d[s].base[0] == d[0].base[0] &&
+                 d[s].num_records[0] == d[0].num_records[0] && d[s].comp_off[0] == d[0].comp_off[0] + 4 * s &&
+                 d[s].guard == d[0].guard && d[s].stride[0] == 12 && d[s].stride[1] == d[0].stride[1] &&
+                 d[s].stride[2] == d[0].stride[2] && d[s].stride[1] < (1 << 23) && d[s].stride[2] < (1 << 23);
+        if (il) return SIG_IL3;
+    }
     int kinds[kMaxSources];
     for (int s = 0; s < dj.n_src; ++s) {
         const DevSource& d = dj.src[s];
@@ -608,6 +622,7 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
         }
         if (!sh.desc.comp[0] && !sh.shadow)
             return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source %d is enabled but has no data", s);
+        dj.src_index[n_act] = s;
         DevSource& ds = dj.src[n_act++];
         ds.packed = sh.packed;
         for (int c = 0; c < 4; ++c) {
@@ -792,8 +807,121 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     return ISAAC_OK;
 }
 
+// Scan points a job is expected to take before clipping and termination:
+// the volume's cells over the step, times the rays per cell cross-section at
+// the volume's centre.
+double estimate_samples(const DevJob& dj) {
+    const double cells = (double)dj.dims[0] * dj.dims[1] * dj.dims[2];
+    double px;   // pixels per voxel across the view at the volume centre
+    if (dj.ortho) {
+        px = dj.height / (2.0 * dj.h);
+    } else {
+        double r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double c = dj.org[a] + 0.5 * dj.dims[a] - dj.eye[a];
+            r2 += c * c;
+        }
+        px = dj.height / (2.0 * std::sqrt(std::max(r2, 1.0)) * dj.h);
+    }
+    return cells / dj.step * std::min(px * px, 1.0e6);
+}
+
+// Replace the sources of the call's jobs by derived volumes where that saves
+// work: each voxel's chain output is then computed once per call instead of
+// once per trilinear corner visit, and the ray loop gathers one interleaved
+// FP32 value per source.  The values are the ones the loop would compute, so
+// the image does not change.
+isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, std::vector<DevJob>& djs, bool force,
+                            hipStream_t stream) {
+    const int n = (int)djs.size();
+    std::vector<int> vols;
+    for (int i = 0; i < n; ++i)
+        if (std::find(vols.begin(), vols.end(), jobs[i].volume_id) == vols.end()) vols.push_back(jobs[i].volume_id);
+    for (int vid : vols) {
+        Volume& v = ctx->volumes[vid];
+        int comp_of[kMaxSources];
+        for (int s = 0; s < kMaxSources; ++s) comp_of[s] = -1;
+        double est = 0.0;
+        bool benefit = false;
+        int g = 0;
+        for (int i = 0; i < n; ++i) {
+            if (jobs[i].volume_id != vid) continue;
+            const DevJob& dj = djs[i];
+            est += estimate_samples(dj) * (dj.interp ? 8.0 : 1.0);
+            for (int k = 0; k < dj.n_src; ++k) {
+                const DevSource& d = dj.src[k];
+                comp_of[dj.src_index[k]] = 0;
+                benefit = benefit || d.f_dim > 1 || d.n_ops > 0 || d.dtype != DT_F32 || !d.packed;
+                g = std::max(g, (int)d.guard);
+            }
+        }
+        int nd = 0;
+        for (int s = 0; s < kMaxSources; ++s)
+            if (comp_of[s] >= 0) comp_of[s] = nd++;
+        if (nd == 0 || nd > kMaxDerived || !benefit) continue;
+        const int64_t ex = v.dims[0] + 2 * g, ey = v.dims[1] + 2 * g, ez = v.dims[2] + 2 * g;
+        const size_t bytes = (size_t)ex * ey * ez * nd * sizeof(float);
+        if (bytes >= ((size_t)1 << 31)) continue;
+        if (!force && est < 4.0 * (double)(ex * ey * ez)) continue;
+        if (v.derived_bytes != bytes) {
+            if (v.derived) {
+                HIP_TRY(ctx, hipStreamSynchronize(stream));
+                HIP_TRY(ctx, hipFree(v.derived));
+            }
+            v.derived = nullptr;
+            v.derived_bytes = 0;
+            if (hipMalloc(&v.derived, bytes) != hipSuccess) {
+                v.derived = nullptr;
+                continue;             // no memory: read the sources directly
+            }
+            v.derived_bytes = bytes;
+        }
+        // the sources as the ray loop would read them, from the first job using each
+        DeriveArgs da;
+        std::memset(&da, 0, sizeof da);
+        da.n = nd;
+        da.g = g;
+        da.ext[0] = (int)ex;
+        da.ext[1] = (int)ey;
+        da.ext[2] = (int)ez;
+        da.dst = static_cast<float*>(v.derived);
+        for (int i = 0; i < n; ++i) {
+            if (jobs[i].volume_id != vid) continue;
+            for (int k = 0; k < djs[i].n_src; ++k) da.src[comp_of[djs[i].src_index[k]]] = djs[i].src[k];
+        }
+        int rc = launch_derive(da, stream);
+        if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "derive launch: %s", hipGetErrorString((hipError_t)rc));
+        const int32_t sx = 4 * nd, sy = (int32_t)(sx * ex), sz = (int32_t)(sy * ey);
+        const int32_t o0 = g * (sx + sy + sz);
+        for (int i = 0; i < n; ++i) {
+            if (jobs[i].volume_id != vid) continue;
+            DevJob& dj = djs[i];
+            for (int k = 0; k < dj.n_src; ++k) {
+                DevSource& d = dj.src[k];
+                const int guard = d.guard;
+                std::memset(d.base, 0, sizeof d.base);
+                std::memset(d.num_records, 0, sizeof d.num_records);
+                std::memset(d.comp_off, 0, sizeof d.comp_off);
+                d.base[0] = reinterpret_cast<uint64_t>(v.derived);
+                d.num_records[0] = (uint32_t)bytes;
+                d.comp_off[0] = o0 + 4 * comp_of[dj.src_index[k]];
+                d.packed = 1;
+                d.stride[0] = sx;
+                d.stride[1] = sy;
+                d.stride[2] = sz;
+                d.f_dim = 1;
+                d.dtype = DT_F32;
+                d.guard = guard;
+                d.n_ops = 0;
+            }
+            if (dj.mode != ISAAC_ISO) dj.sig = signature_of(dj);
+        }
+    }
+    return ISAAC_OK;
+}
+
 isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int n, unsigned flags, bool need_out,
-                         hipStream_t stream) {
+                         hipStream_t stream, bool allow_derive) {
     if (n < 1 || n > kMaxBatch || !jobs)
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "n_jobs must be 1..%d", kMaxBatch);
     std::vector<DevJob> djs(n);
@@ -809,12 +937,8 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
     // non-persistent sources read their shadow copies
     for (int i = 0; i < n; ++i) {
         const Volume& v = ctx->volumes[jobs[i].volume_id];
-        int k = 0;
-        for (int s = 0; s < (int)v.src.size(); ++s) {
-            const SourceHost& sh = v.src[s];
-            const bool en = jobs[i].enabled ? jobs[i].enabled[s] != 0 : sh.desc.enabled != 0;
-            const float w = jobs[i].weights ? jobs[i].weights[s] : sh.desc.weight;
-            if (!en || w == 0.0f) continue;
+        for (int k = 0; k < djs[i].n_src; ++k) {
+            const SourceHost& sh = v.src[djs[i].src_index[k]];
             if (!sh.desc.persistent) {
                 DevSource& ds = djs[i].src[k];
                 const int es = esize_of(sh.desc.dtype);
@@ -828,8 +952,11 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
                 for (int c = 0; c < 4; ++c) ds.comp_off[c] = o + c * es;
                 ds.packed = 1;
             }
-            ++k;
         }
+    }
+    if (allow_derive && !(flags & ISAAC_DIRECT)) {
+        st = derive_volumes(ctx, jobs, djs, (flags & ISAAC_DERIVE) != 0, stream);
+        if (st) return st;
     }
     // one launch per scan-point schedule, so every job is rendered exactly as
     // it would be alone (its size class's lanes per ray, unroll and variant)
@@ -962,9 +1089,11 @@ void isaac_destroy(isaac_context* ctx) {
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     for (hipStream_t s : ctx->serve_streams) hipStreamSynchronize(s);
     hipDeviceSynchronize();
-    for (auto& v : ctx->volumes)
+    for (auto& v : ctx->volumes) {
         for (auto& s : v.src)
             if (s.shadow) hipFree(s.shadow);
+        if (v.derived) hipFree(v.derived);
+    }
     for (auto& kv : ctx->tickets) {
         if (kv.second.out) hipFree(kv.second.out);
         if (kv.second.ev) hipEventDestroy(kv.second.ev);
@@ -1067,6 +1196,9 @@ isaac_status isaac_set_sources(isaac_context* ctx, int volume_id, const int32_t 
         hipStreamSynchronize(ctx->stream);
         for (auto& s : v.src)
             if (s.shadow) hipFree(s.shadow);
+        if (v.derived) hipFree(v.derived);
+        v.derived = nullptr;
+        v.derived_bytes = 0;
     }
     std::vector<int32_t> tf(n_src, 0);
     for (int s = 0; s < n_src && s < (int)v.tf.size(); ++s) tf[s] = v.tf[s];
@@ -1110,7 +1242,7 @@ isaac_status isaac_release_transfer(isaac_context* ctx, int32_t handle) {
 isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags) {
     isaac_status st = check_ctx(ctx);
     if (st) return st;
-    return render_impl(ctx, jobs, n_jobs, flags, true, ctx->stream);
+    return render_impl(ctx, jobs, n_jobs, flags, true, ctx->stream, true);
 }
 
 isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const float* const* depth, int n_layers,
@@ -1239,7 +1371,7 @@ isaac_status isaac_submit_batch(isaac_context* ctx, const isaac_render_desc* job
     }
     hipStream_t s = ctx->serve_streams[ctx->serve_rr];
     ctx->serve_rr = (ctx->serve_rr + 1) % (int)ctx->serve_streams.size();
-    st = render_impl(ctx, js.data(), n, ISAAC_ASYNC | ISAAC_NO_GRAPH, true, s);
+    st = render_impl(ctx, js.data(), n, ISAAC_ASYNC | ISAAC_NO_GRAPH, true, s, false);
     if (st) {
         for (auto& m : made) {
             ctx->image_cache.emplace(m.bytes, m.out);

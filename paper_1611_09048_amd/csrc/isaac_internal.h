@@ -44,6 +44,7 @@ enum Signature : int32_t {
     SIG_PIC3_F32 = 2,     // FP32 scalar, FP32 3-vector, FP32 3-vector
     SIG_PIC3_F16 = 3,     // the same in FP16
     SIG_PIC3_BF16 = 4,    // the same in BF16
+    SIG_IL3 = 5,          // three FP32 scalars interleaved in one buffer (a derived volume)
 };
 
 struct DevSource {
@@ -95,6 +96,7 @@ struct DevJob {
     float* out;            // device RGBA32F image
     int32_t* out_samples;  // device per-pixel sample counts or null
     float* out_depth;      // device per-pixel ray parameter of the first scan point (+inf: none) or null
+    int32_t src_index[kMaxSources];  // volume source index of each active source (host bookkeeping)
     DevSource src[kMaxSources];
 };
 
@@ -121,6 +123,18 @@ int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, 
                         const int64_t* dst_stride, int esize, int f_dim, const int32_t lo[3],
                         const int32_t ext[3], void* stream);
 int raycast_occupancy(int* blocks_per_cu);
+
+// Derived volume: the functor-chain output of up to 4 sources at every voxel
+// of [-g, N-1+g]^3, interleaved (n floats per voxel, x fastest).
+constexpr int kMaxDerived = 4;
+struct DeriveArgs {
+    DevSource src[kMaxDerived];   // as the ray loop would read them
+    int n;                        // sources (components per voxel)
+    int g;                        // guard layers covered
+    int ext[3];                   // N + 2g per axis
+    float* dst;
+};
+int launch_derive(const DeriveArgs& a, void* stream);
 constexpr int kMaxLayers = 16;
 int launch_composite(const float* const* rgba, const float* const* depth, int n_layers, int64_t n_pixels,
                      float* out, void* stream);

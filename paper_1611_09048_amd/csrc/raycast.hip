@@ -502,6 +502,7 @@ template <> struct SigKinds<SIG_F32x1> { static constexpr int k0 = K_F32x1, k1 =
 template <> struct SigKinds<SIG_PIC3_F32> { static constexpr int k0 = K_F32x1, k1 = K_F32x3, k2 = K_F32x3; };
 template <> struct SigKinds<SIG_PIC3_F16> { static constexpr int k0 = K_F16x1, k1 = K_F16x3, k2 = K_F16x3; };
 template <> struct SigKinds<SIG_PIC3_BF16> { static constexpr int k0 = K_BF16x1, k1 = K_BF16x3, k2 = K_BF16x3; };
+template <> struct SigKinds<SIG_IL3> { static constexpr int k0 = K_F32x1, k1 = K_F32x1, k2 = K_F32x1; };
 
 // PS (per source): load, chain, blend and classify one source before the
 // next one's loads; fewer live registers (more resident waves) at the cost of
@@ -550,7 +551,23 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
             E[u][1] = fmaf(wa, cl.y, E[u][1]);
             E[u][2] = fmaf(wa, cl.z, E[u][2]);
         };
-        if constexpr (PS) {
+        if constexpr (SIG == SIG_IL3) {
+            // the three chain outputs of a voxel are adjacent: one 12-byte load per corner
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int off[NV];
+                float v[NV][4];
+                corner_offsets<INTERP>(J.src[0], dims, i0[u], off);
+                fetch_kind<K_F32x3, NV>(J.src[0], off, v);
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    float c[NV];
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) c[i] = v[i][s];
+                    accumulate(u, s, blend<NV>(c, wts[u]));
+                }
+            }
+        } else if constexpr (PS) {
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
 #pragma unroll
@@ -716,6 +733,7 @@ __device__ __forceinline__ void march_dispatch(const DevJob& J, const float4* __
     case SIG_PIC3_F32: march_sig<INTERP, U, G, SIG_PIC3_F32, PS>(J, s_tf, R, lane, out, count); break;
     case SIG_PIC3_F16: march_sig<INTERP, U, G, SIG_PIC3_F16, PS>(J, s_tf, R, lane, out, count); break;
     case SIG_PIC3_BF16: march_sig<INTERP, U, G, SIG_PIC3_BF16, PS>(J, s_tf, R, lane, out, count); break;
+    case SIG_IL3: march_sig<INTERP, U, G, SIG_IL3, PS>(J, s_tf, R, lane, out, count); break;
     default: march_sig<INTERP, U, G, SIG_GENERIC, PS>(J, s_tf, R, lane, out, count); break;
     }
 }
@@ -953,6 +971,32 @@ __global__ void encode_rgba8_kernel(EncodeArgs a) {
     }
 }
 
+// Derived volume: every voxel's chain output per source, computed once with
+// the same fetch and chain code as the ray loop (so the values are the ones
+// the loop would compute at that voxel, bit for bit).  One thread per voxel,
+// x fastest: reads and the interleaved writes are coalesced.
+__global__ void derive_kernel(DeriveArgs a) {
+    const int64_t ex = a.ext[0], ey = a.ext[1];
+    const int64_t n = ex * ey * a.ext[2];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % ex) - a.g;
+        const int y = (int)((i / ex) % ey) - a.g;
+        const int z = (int)(i / (ex * ey)) - a.g;
+        for (int s = 0; s < a.n; ++s) {
+            const DevSource& S = a.src[s];
+            // a source without guard layers never has them read: its guard cells hold the border values
+            const int qx = S.guard < 1 ? clampi(x, 0, a.ext[0] - 2 * a.g - 1) : x;
+            const int qy = S.guard < 1 ? clampi(y, 0, a.ext[1] - 2 * a.g - 1) : y;
+            const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
+            const int off[1] = {qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2]};
+            float v[1][4], r[1];
+            fetch<1>(S, off, v);
+            run_chain<1>(S, v, r);
+            a.dst[i * a.n + s] = r[0];
+        }
+    }
+}
+
 __global__ void reset_counter_kernel(int* c) {
     if (threadIdx.x == 0) c[0] = 0;
 }
@@ -1007,6 +1051,7 @@ KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
     case SIG_PIC3_F32: return pick_specialized<SIG_PIC3_F32>(unroll, lanes, hint);
     case SIG_PIC3_F16: return pick_specialized<SIG_PIC3_F16>(unroll, lanes, hint);
     case SIG_PIC3_BF16: return pick_specialized<SIG_PIC3_BF16>(unroll, lanes, hint);
+    case SIG_IL3: return pick_specialized<SIG_IL3>(unroll, lanes, hint);
     default:
         break;
     }
@@ -1085,6 +1130,14 @@ int launch_encode_rgba8(const float* rgba, int64_t n_pixels, const float* bg, un
     const int64_t blocks = std::min<int64_t>((n_pixels + 255) / 256, 8192);
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(encode_rgba8_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
+    return hipGetLastError();
+}
+
+int launch_derive(const DeriveArgs& a, void* stream) {
+    const int64_t n = (int64_t)a.ext[0] * a.ext[1] * a.ext[2];
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(derive_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,112 @@
+"""Derived volumes: each active source's functor chain evaluated once per voxel
+into an interleaved FP32 buffer that the ray loop then reads.  The loop would
+compute the same values at every corner it visits, so a render through the
+derived volume (ISAAC_DERIVE) must equal the direct render (ISAAC_DIRECT) bit
+for bit, images and sample counts, in every mode and schedule.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import compare, log
+from scenes import configs, make_source, relayout
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1611_09048_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(device=0)
+    yield c
+    c.close()
+
+
+def both(ctx, sc, vid=0, **overrides):
+    from paper_1611_09048_amd import DERIVE, DIRECT, device
+    a = device.render_scene(ctx, sc, volume_id=vid, flags=DIRECT, **overrides)
+    b = device.render_scene(ctx, sc, volume_id=vid, flags=DERIVE, **overrides)
+    return a, b
+
+
+def assert_same(a, b, label):
+    same_img = np.array_equal(a[0], b[0], equal_nan=True)
+    same_cnt = a[1] is None or np.array_equal(a[1], b[1])
+    log(f"derived vs direct {label}: max |diff| = {np.nanmax(np.abs(a[0] - b[0])):.3e}, counts equal {same_cnt}")
+    assert same_img and same_cnt, label
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("interpolation", [1, 0])
+def test_derived_equals_direct(ctx, dtype, interpolation):
+    sc = configs.pic3(n=40, width=128, height=96, dtype=dtype).with_(interpolation=interpolation)
+    a, b = both(ctx, sc)
+    assert_same(a, b, f"pic3 {dtype} interp={interpolation}")
+    if dtype == "f32" and interpolation == 1:
+        compare(b[0].reshape(-1, 4), b[1].reshape(-1), oracle.render(sc, threads=8), label="derived vs oracle")
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 16])
+def test_derived_every_schedule(ctx, lanes):
+    from paper_1611_09048_amd import autotune
+    sc = configs.pic3(n=40, width=128, height=96, direction=(-0.6, 0.3, 0.7))
+    cls = autotune.size_class(sc.width, sc.height)
+    old = ctx.get_tile_shape(cls)
+    try:
+        ctx.set_tile_shape(cls, 4 if lanes == 16 else 8, 2, 1, lanes, 0)
+        a, b = both(ctx, sc)
+        assert_same(a, b, f"lanes={lanes}")
+    finally:
+        ctx.set_tile_shape(cls, *old)
+
+
+def test_derived_with_disabled_source_layouts_and_guardless(ctx):
+    """A disabled middle source (components map around it), SoA and permuted
+    layouts, a guard-less source and a non-persistent one."""
+    from paper_1611_09048_amd import device
+    base = configs.pic3(n=36, width=96, height=80)
+    s0, s1, s2 = base.sources
+    s1 = relayout(s1, layout="soa", order=(2, 0, 1))
+    inner = s2.values[1:-1, 1:-1, 1:-1]
+    s2g0 = make_source("B0", inner.astype(np.float32), guard=0, chain=s2.chain, weight=s2.weight, tf=s2.tf,
+                       persistent=False)
+    sc = base.with_(sources=[s0, s1, s2g0])
+    a, b = both(ctx, sc, vid=3)
+    assert_same(a, b, "soa/permuted + guard-less non-persistent")
+    a, b = both(ctx, sc, vid=4, enabled=[True, False, True])
+    assert_same(a, b, "middle source disabled")
+
+
+def test_derived_iso_mode(ctx):
+    sc = configs.pic3(n=40, width=128, height=96)
+    sc = sc.with_(mode="iso", sources=[dataclasses.replace(s, iso=v) for s, v in
+                                       zip(sc.sources, (1.0, 0.2, float("nan")))])
+    a, b = both(ctx, sc, vid=5)
+    assert_same(a, b, "iso")
+
+
+def test_derived_batch_of_views(ctx):
+    """Several jobs on one volume with different enabled sets share one derived volume."""
+    import torch
+    from paper_1611_09048_amd import DERIVE, DIRECT, device
+    sc = configs.pic3(n=40, width=112, height=80)
+    vol = device.upload_volume(ctx, sc, 6)
+    views = [configs.D0, (0.2, -0.9, 0.4), (-0.7, -0.1, -0.7)]
+    enabled = [None, [True, False, True], [False, True, True]]
+    out = {}
+    for flags in (DIRECT, DERIVE):
+        imgs = [device.new_image(sc) for _ in views]
+        jobs = [device.render_job(sc.with_(camera=configs.orbit_camera(sc.dims, v)), 6, im, enabled=e)
+                for v, im, e in zip(views, imgs, enabled)]
+        for _ in range(3):                      # graph replays included
+            ctx.render(jobs, flags)
+        torch.cuda.synchronize()
+        out[flags] = [im.cpu().numpy() for im in imgs]
+    for k in range(len(views)):
+        assert np.array_equal(out[DIRECT][k], out[DERIVE][k]), k
+    del vol
