@@ -235,16 +235,17 @@ isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count);
 /* Ray-tile shape and scan-point schedule for jobs of one image-size class
  * (the autotuner's output).  size_class = ceil(log2(max(width,height)))
  * clamped to [0,15].
- *   lanes_per_ray in {1,2,4,8,16}: lanes sharing one ray, each taking every
- *     lanes_per_ray-th scan point (more parallelism where few rays meet the
- *     volume); a 64-lane wave holds 64/lanes_per_ray rays;
- *   wave_w, a power of two in [2, 64/lanes_per_ray]: a wave's rays form a
+ *   lanes_per_ray in {1,2,4,8,16,32,64}: lanes sharing one ray, each taking
+ *     every lanes_per_ray-th scan point (more parallelism where few rays meet
+ *     the volume); a 64-lane wave holds 64/lanes_per_ray rays;
+ *   wave_w, a power of two in [1, 64/lanes_per_ray]: a wave's rays form a
  *     wave_w x (64/lanes_per_ray/wave_w) pixel block;
  *   waves_x in {1,2,4}: the 4 waves of a workgroup are waves_x x 4/waves_x;
  *   unroll in {1,2} (one lane per ray only): scan points whose source reads
  *     are issued together;
  *   min_waves in {0,4}: 4 selects the kernel variant compiled to keep at
- *     least 4 waves resident per SIMD (not with lanes_per_ray 2 or unroll 2).
+ *     least 4 waves resident per SIMD (not with lanes_per_ray 2, 32, 64 or
+ *     unroll 2).
  * A batch runs one launch per distinct schedule, so each job is rendered as
  * it would be alone.
  * Defaults: (8, 2, 1, 1, 0).  Settings with one lane per ray give the same

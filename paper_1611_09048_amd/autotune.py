@@ -5,8 +5,10 @@ For every size class present in a workload it times the ray-casting kernel
 (wave_w, waves_x, unroll, lanes_per_ray, min_waves) and keeps the fastest.  Results are cached as JSON
 keyed by device architecture, size class and a source signature (source
 count, storage types, feature dimensions, interpolation), and applied with
-isaac_set_tile_shape.  Tile shape and schedule never change an image: every
-candidate produces the same pixels bit for bit.
+isaac_set_tile_shape.  Tile shapes with one lane per ray produce the same
+pixels bit for bit; more lanes per ray composite each row of scan points by
+a scan, which changes FP32 rounding only (every setting reproduces its own
+image bit for bit).
 """
 
 from __future__ import annotations
@@ -18,10 +20,10 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
 from . import binding
 
-WAVE_W = (2, 4, 8, 16, 32, 64)
+WAVE_W = (1, 2, 4, 8, 16, 32, 64)
 WAVES_X = (1, 2, 4)
 UNROLL = (1, 2)
-LANES = (1, 2, 4, 8, 16)
+LANES = (1, 2, 4, 8, 16, 32, 64)
 MIN_WAVES = (0, 4)
 DEFAULT = (8, 2, 1, 1, 0)
 
@@ -38,7 +40,7 @@ def candidates(unrolls: Sequence[int] = UNROLL, lanes: Sequence[int] = LANES, wa
     for g in lanes:
         for u in (unrolls if g == 1 else (1,)):
             for m in min_waves:
-                if m and (g == 2 or u == 2):
+                if m and (g == 2 or g >= 32 or u == 2):
                     continue
                 for w in wave_ws:
                     if w <= 64 // g and (w >= 8 or w == 64 // g):

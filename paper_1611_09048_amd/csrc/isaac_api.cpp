@@ -740,7 +740,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     la.max_src = std::max(1, max_src);
     la.unroll = unroll;
     la.lanes = lanes;
-    la.waves_hint = (lanes == 2 || unroll > 1) ? 0 : hint;
+    la.waves_hint = (lanes == 2 || lanes >= 32 || unroll > 1) ? 0 : hint;
     la.sig = djs[0].sig;
     for (const DevJob& dj : djs)
         if (dj.sig != la.sig) la.sig = -1;
@@ -1299,11 +1299,11 @@ isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w
                                   int lanes_per_ray, int min_waves) {
     if (!ctx) return ISAAC_ERR_INVALID_ARGUMENT;
     const int g = lanes_per_ray;
-    const bool lanes_ok = g == 1 || g == 2 || g == 4 || g == 8 || g == 16;
-    const bool ww_ok = wave_w >= 2 && wave_w <= 64 && (wave_w & (wave_w - 1)) == 0 && lanes_ok && wave_w <= 64 / g;
+    const bool lanes_ok = g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64;
+    const bool ww_ok = wave_w >= 1 && wave_w <= 64 && (wave_w & (wave_w - 1)) == 0 && lanes_ok && wave_w <= 64 / g;
     if (size_class < 0 || size_class > 15 || !ww_ok || (waves_x != 1 && waves_x != 2 && waves_x != 4) ||
         (unroll != 1 && unroll != 2) || (g > 1 && unroll != 1) || (min_waves != 0 && min_waves != 4) ||
-        (min_waves == 4 && (g == 2 || unroll == 2)))
+        (min_waves == 4 && (g == 2 || g >= 32 || unroll == 2)))
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "invalid tile shape");
     ctx->shapes[size_class] = TileShape{wave_w, waves_x, unroll, g, min_waves == 4 ? 1 : 0};
     return ISAAC_OK;

@@ -649,11 +649,17 @@ __device__ __forceinline__ void march_seq(const DevJob& J, const float4* __restr
     count = n;
 }
 
-// Shift within rows of 16 lanes (DPP row_shr:d); lanes below d receive 0.
+// Value of the lane D below (DPP row_shr:D inside rows of 16 lanes; a
+// bpermute for D = 16, 32).  Lanes whose source lies outside their group of
+// G are never combined, so what they receive does not matter.
 template <int D>
-__device__ __forceinline__ float row_shr(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x110 + D, 0xF, 0xF,
-                                                                 true));
+__device__ __forceinline__ float lane_up(float x) {
+    if constexpr (D < 16) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x110 + D, 0xF,
+                                                                     0xF, true));
+    } else {
+        return __shfl_up(x, D, 64);
+    }
 }
 
 // G lanes per ray: lane g evaluates scan points kb + g, kb + g + G, ...; each
@@ -681,13 +687,17 @@ __device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __res
         for (int d = 1; d < G; d <<= 1) {
             float o0, o1, o2, oa;
             if (d == 1) {
-                o0 = row_shr<1>(c0); o1 = row_shr<1>(c1); o2 = row_shr<1>(c2); oa = row_shr<1>(a);
+                o0 = lane_up<1>(c0); o1 = lane_up<1>(c1); o2 = lane_up<1>(c2); oa = lane_up<1>(a);
             } else if (d == 2) {
-                o0 = row_shr<2>(c0); o1 = row_shr<2>(c1); o2 = row_shr<2>(c2); oa = row_shr<2>(a);
+                o0 = lane_up<2>(c0); o1 = lane_up<2>(c1); o2 = lane_up<2>(c2); oa = lane_up<2>(a);
             } else if (d == 4) {
-                o0 = row_shr<4>(c0); o1 = row_shr<4>(c1); o2 = row_shr<4>(c2); oa = row_shr<4>(a);
+                o0 = lane_up<4>(c0); o1 = lane_up<4>(c1); o2 = lane_up<4>(c2); oa = lane_up<4>(a);
+            } else if (d == 8) {
+                o0 = lane_up<8>(c0); o1 = lane_up<8>(c1); o2 = lane_up<8>(c2); oa = lane_up<8>(a);
+            } else if (d == 16) {
+                o0 = lane_up<16>(c0); o1 = lane_up<16>(c1); o2 = lane_up<16>(c2); oa = lane_up<16>(a);
             } else {
-                o0 = row_shr<8>(c0); o1 = row_shr<8>(c1); o2 = row_shr<8>(c2); oa = row_shr<8>(a);
+                o0 = lane_up<32>(c0); o1 = lane_up<32>(c1); o2 = lane_up<32>(c2); oa = lane_up<32>(a);
             }
             if (g >= d) {
                 const float t = 1.f - oa;
@@ -700,10 +710,11 @@ __device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __res
         const float T = 1.f - A;
         const float n0 = fmaf(T, c0, Cr), n1 = fmaf(T, c1, Cg), n2 = fmaf(T, c2, Cb), na = fmaf(T, a, A);
         const unsigned long long m = __ballot(valid && na >= ert);
-        const unsigned bits = (unsigned)(m >> (lane & ~(G - 1))) & ((1u << G) - 1u);
+        constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull);
+        const unsigned long long bits = (m >> (lane & ~(G - 1))) & kGroupMask;
         int sel;
         if (bits) {
-            sel = __builtin_ctz(bits);
+            sel = __builtin_ctzll(bits);
             stop = true;
         } else {
             sel = min(G, R.ke - k0) - 1;
@@ -1036,6 +1047,8 @@ template <int SIGK>
 KernelFn pick_specialized(int unroll, int lanes, int hint) {
     if (unroll >= 2) return raycast_kernel<2, 1, 0, SIGK>;
     switch (lanes) {
+    case 64: return raycast_kernel<1, 64, 0, SIGK>;
+    case 32: return raycast_kernel<1, 32, 0, SIGK>;
     case 16: return hint ? raycast_kernel<1, 16, 4, SIGK> : raycast_kernel<1, 16, 0, SIGK>;
     case 8: return hint ? raycast_kernel<1, 8, 4, SIGK> : raycast_kernel<1, 8, 0, SIGK>;
     case 4: return hint ? raycast_kernel<1, 4, 4, SIGK> : raycast_kernel<1, 4, 0, SIGK>;
@@ -1057,6 +1070,8 @@ KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
     }
     // mixed or generic signatures: the dispatching kernels (one lane-count each)
     switch (lanes) {
+    case 64: return raycast_kernel<1, 64, 0, -1>;
+    case 32: return raycast_kernel<1, 32, 0, -1>;
     case 16: return raycast_kernel<1, 16, 0, -1>;
     case 8: return raycast_kernel<1, 8, 0, -1>;
     case 4: return raycast_kernel<1, 4, 0, -1>;

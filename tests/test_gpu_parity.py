@@ -228,7 +228,8 @@ def test_tile_shapes_and_schedules(ctx):
             img, cnt = gpu_render(ctx, sc)
             assert np.array_equal(img, ref) and np.array_equal(cnt, refc), (ww, wx, u)
         for ww, wx, g, m in ((8, 2, 2, 0), (16, 1, 2, 0), (8, 4, 4, 0), (16, 2, 4, 4), (32, 1, 2, 0), (8, 1, 8, 0),
-                             (4, 2, 16, 4), (8, 2, 8, 4), (4, 4, 16, 0), (8, 4, 1, 4)):
+                             (4, 2, 16, 4), (8, 2, 8, 4), (4, 4, 16, 0), (8, 4, 1, 4), (2, 2, 32, 0), (1, 4, 32, 0),
+                             (1, 1, 64, 0), (1, 4, 64, 0)):
             ctx.set_tile_shape(cls, ww, wx, 1, g, m)
             img, cnt = gpu_render(ctx, sc)
             compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=f"lanes={g} wave_w={ww} waves_x={wx} min_waves={m}")
@@ -240,9 +241,9 @@ def test_tile_shapes_and_schedules(ctx):
 
 
 def test_lanes_per_ray_full_parity(ctx):
-    """Every feature under 2 and 4 lanes per ray (random tiny scenes) against the oracle."""
+    """Every feature under 2 to 64 lanes per ray (random tiny scenes) against the oracle."""
     try:
-        for g in (2, 4, 16):
+        for g in (2, 4, 16, 32, 64):
             for c in range(16):
                 ctx.set_tile_shape(c, min(8, 64 // g), 2, 1, g, 0)
             for seed in range(20):
