@@ -502,6 +502,51 @@ void set_tiles(DevJob& dj, int lanes, int unroll) {
     dj.tiles_y = (dj.height + th - 1) / th;
 }
 
+// A pixel rectangle containing every pixel whose ray can meet the box (the
+// local box, or the brick's box in the global index space): the projections
+// of the 8 box corners bound the projection of the convex box, widened by one
+// pixel.  A corner at or behind the eye plane disables the test.
+void set_cull_rect(DevJob& dj) {
+    dj.cull[0] = 0;
+    dj.cull[1] = 0;
+    dj.cull[2] = dj.width - 1;
+    dj.cull[3] = dj.height - 1;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = dj.org[a];
+        hi[a] = (double)dj.org[a] + dj.dims[a];
+    }
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (int c = 0; c < 8; ++c) {
+        double v[3];
+        for (int a = 0; a < 3; ++a) v[a] = ((c >> a) & 1 ? hi[a] : lo[a]) - dj.eye[a];
+        const double vr = v[0] * dj.right[0] + v[1] * dj.right[1] + v[2] * dj.right[2];
+        const double vu = v[0] * dj.upp[0] + v[1] * dj.upp[1] + v[2] * dj.upp[2];
+        double x, y;
+        if (dj.ortho) {
+            x = vr / (dj.h * dj.aspect);
+            y = vu / dj.h;
+        } else {
+            const double z = v[0] * dj.fwd[0] + v[1] * dj.fwd[1] + v[2] * dj.fwd[2];
+            const double vl = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (!(z > 1e-6 * (vl + 1.0))) return;
+            x = vr / (z * dj.h * dj.aspect);
+            y = vu / (z * dj.h);
+        }
+        const double pi = (x + 1.0) * 0.5 * dj.width - 0.5;
+        const double pj = (1.0 - y) * 0.5 * dj.height - 0.5;
+        xmin = std::min(xmin, pi);
+        xmax = std::max(xmax, pi);
+        ymin = std::min(ymin, pj);
+        ymax = std::max(ymax, pj);
+    }
+    auto clampd = [](double v, double a, double b) { return std::min(std::max(v, a), b); };
+    dj.cull[0] = (int)clampd(std::floor(xmin) - 1.0, 0.0, (double)dj.width);
+    dj.cull[1] = (int)clampd(std::floor(ymin) - 1.0, 0.0, (double)dj.height);
+    dj.cull[2] = (int)clampd(std::ceil(xmax) + 1.0, -1.0, (double)dj.width - 1);
+    dj.cull[3] = (int)clampd(std::ceil(ymax) + 1.0, -1.0, (double)dj.height - 1);
+}
+
 int size_class_of(int w, int h) {
     int m = std::max(w, h), c = 0;
     while ((1 << c) < m && c < 15) ++c;
@@ -595,6 +640,7 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
         dj.brick = 0;
     }
     dj.out_depth = j.out_depth;
+    set_cull_rect(dj);
     const TileShape& ts = ctx->shapes[size_class_of(j.width, j.height)];
     dj.wave_w = ts.wave_w;
     dj.waves_x = ts.waves_x;

@@ -93,6 +93,7 @@ struct DevJob {
     int32_t mode;          // 0 volume compositing, 1 first iso-surface
     int32_t tiles_x, tiles_y;
     int32_t tile_begin;    // first tile index of this job in the batch
+    int32_t cull[4];       // pixels [cull[0], cull[2]] x [cull[1], cull[3]] hold every ray that can meet the box
     float* out;            // device RGBA32F image
     int32_t* out_samples;  // device per-pixel sample counts or null
     float* out_depth;      // device per-pixel ray parameter of the first scan point (+inf: none) or null

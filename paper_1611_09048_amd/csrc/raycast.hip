@@ -861,8 +861,10 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         const DevJob& J = jobs[job];
         int px = 0, py = 0;
         const bool in_image = pixel_of<G>(J, tile - J.tile_begin, lane, wave, px, py);
+        // pixels outside the box's screen rectangle skip the FP64 setup
+        const bool in_rect = px >= J.cull[0] && px <= J.cull[2] && py >= J.cull[1] && py <= J.cull[3];
         RaySetup R;
-        const bool hit = in_image && setup_ray(J, px, py, R);
+        const bool hit = in_image && in_rect && setup_ray(J, px, py, R);
         // tiles no ray of which meets the box skip the transfer tables; the
         // barrier also ends every read of the previous tile's tables
         if (__syncthreads_or(hit) && job != cur_job) {

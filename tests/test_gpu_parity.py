@@ -283,3 +283,27 @@ def test_mirror_symmetry(ctx):
     img, _ = gpu_render(ctx, sc)
     assert img[..., 3].max() > 0.05
     assert np.allclose(img, img[:, ::-1], atol=2e-3)
+
+
+def test_screen_rectangle_culling_is_conservative(ctx):
+    """Rays outside the box's projected rectangle are skipped: for cameras that put
+    the box at the image border, partly off screen, very close (corners behind
+    the eye) or far, every pixel with samples in the oracle has them on the GPU."""
+    rng = np.random.default_rng(77)
+    base = configs.plain_scalar(n=12, width=40, height=30)
+    dims = np.array(base.dims, dtype=np.float64)
+    for k in range(24):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        dist = float(rng.choice([0.3, 0.9, 1.5, 4.0, 12.0])) * np.linalg.norm(dims)
+        centre = dims / 2 + rng.uniform(-0.6, 0.6, size=3) * dims     # aim off-centre: box near the border
+        eye = centre + dist * d
+        ortho = k % 4 == 3
+        up = (0.0, 0.0, 1.0) if abs(d[2]) < 0.9 else (0.0, 1.0, 0.0)
+        from scenes import Camera
+        cam = Camera(eye=tuple(eye), center=tuple(centre), up=up, fovy_deg=float(rng.uniform(20, 100)),
+                     projection="orthographic" if ortho else "perspective", ortho_height=float(rng.uniform(6, 30)))
+        sc = base.with_(camera=cam, width=int(rng.integers(7, 48)), height=int(rng.integers(5, 40)))
+        img, cnt = gpu_render(ctx, sc)
+        rec = oracle.render(sc)
+        compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=f"culling camera {k}")
