@@ -39,7 +39,7 @@ METRIC = "ray samples/sec (Gsamples/s) + frames/s at 1920x1080; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 TUNED = os.path.join(ROOT, "paper_1611_09048_amd", "tuned_gfx950.json")
 # candidates the bench tunes over when its cache has no entry
-QUICK = dict(lanes=(4, 8, 16), wave_ws=(4, 8, 16), waves_xs=(1, 2, 4), unrolls=(1,), min_waves=(0, 4))
+QUICK = dict(lanes=(4, 8, 16, 32), wave_ws=(2, 4, 8, 16), waves_xs=(1, 2, 4), unrolls=(1,), min_waves=(0, 4))
 
 
 def log(*a):
@@ -138,6 +138,16 @@ def frames(ctx, sc, steps, warmup, log_prefix=""):
         hit.append(float((c > 0).float().mean().item()))
     ctx.render([device.render_job(scenes_v[0], 0, img, cnt)])
     counts_view0 = cnt.cpu().numpy()
+    # what clipping and early termination remove (view 0, untimed)
+    ctx.render([device.render_job(scenes_v[0], 0, img, cnt, ert_threshold=2.0)])
+    no_ert = int(cnt.to(torch.int64).sum().item())
+    ctx.render([device.render_job(scenes_v[0].with_(clip=[]), 0, img, cnt, ert_threshold=2.0)])
+    no_clip_no_ert = int(cnt.to(torch.int64).sum().item())
+    ctx.render([device.render_job(scenes_v[0], 0, img, cnt)])
+    removed = dict(samples_view0=int(counts_view0.sum()), without_termination=no_ert,
+                   without_clip_or_termination=no_clip_no_ert,
+                   clipped_fraction=round(1.0 - no_ert / max(no_clip_no_ert, 1), 4),
+                   terminated_fraction=round(1.0 - int(counts_view0.sum()) / max(no_ert, 1), 4))
     log(f"bench:{log_prefix} samples/frame mean {np.mean(samples):.4g} (min {min(samples)}, max {max(samples)}); "
         f"hit fraction {np.mean(hit):.3f}; tile shape {shape}")
     for k in range(warmup):
@@ -164,7 +174,7 @@ def frames(ctx, sc, steps, warmup, log_prefix=""):
     per_view = per_view[reps > 0] / reps[reps > 0]
     out = dict(gsps=total / elapsed / 1e9, elapsed=elapsed, kernel_ms=kernel_ms / max(n_kernels, 1),
                frame_ms=frame_ms, per_view=per_view, samples=samples, shape=shape, counts_view0=counts_view0,
-               scene_v0=scenes_v[0], field_bytes=sum(s.field_bytes() for s in sc.sources),
+               scene_v0=scenes_v[0], field_bytes=sum(s.field_bytes() for s in sc.sources), removed=removed,
                image_bytes=sc.width * sc.height * 16)
     log(f"bench:{log_prefix} {steps} frames in {elapsed * 1e3:.1f} ms -> {out['gsps']:.2f} Gsamples/s; "
         f"kernel avg {out['kernel_ms']:.4f} ms")
@@ -380,7 +390,7 @@ def main():
                                p99=round(float(np.percentile(fr["frame_ms"], 99)), 4)),
                views_ms=dict(avg=round(float(fr["per_view"].mean()), 4), min=round(float(fr["per_view"].min()), 4),
                              max=round(float(fr["per_view"].max()), 4)),
-               samples_per_frame=int(np.mean(fr["samples"])),
+               samples_per_frame=int(np.mean(fr["samples"])), sample_reduction_view0=fr["removed"],
                roofline=roofline)
     if not args.no_extras:
         extras = {}

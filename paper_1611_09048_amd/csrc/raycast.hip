@@ -649,17 +649,12 @@ __device__ __forceinline__ void march_seq(const DevJob& J, const float4* __restr
     count = n;
 }
 
-// Value of the lane D below (DPP row_shr:D inside rows of 16 lanes; a
-// bpermute for D = 16, 32).  Lanes whose source lies outside their group of
-// G are never combined, so what they receive does not matter.
+// Value of the lane D below inside a row of 16 lanes (DPP row_shr:D); lanes
+// whose source would lie in another row are never combined.
 template <int D>
 __device__ __forceinline__ float lane_up(float x) {
-    if constexpr (D < 16) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x110 + D, 0xF,
-                                                                     0xF, true));
-    } else {
-        return __shfl_up(x, D, 64);
-    }
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x110 + D, 0xF, 0xF,
+                                                                 true));
 }
 
 // G lanes per ray: lane g evaluates scan points kb + g, kb + g + G, ...; each
@@ -683,8 +678,9 @@ __device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __res
         points<INTERP, 1, SIG, PS>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
         float c0 = valid ? E[0][0] : 0.f, c1 = valid ? E[0][1] : 0.f, c2 = valid ? E[0][2] : 0.f;
         float a = valid ? S[0] : 0.f;
+        // inclusive scan inside each row of 16 lanes ...
 #pragma unroll
-        for (int d = 1; d < G; d <<= 1) {
+        for (int d = 1; d < (G < 16 ? G : 16); d <<= 1) {
             float o0, o1, o2, oa;
             if (d == 1) {
                 o0 = lane_up<1>(c0); o1 = lane_up<1>(c1); o2 = lane_up<1>(c2); oa = lane_up<1>(a);
@@ -692,14 +688,25 @@ __device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __res
                 o0 = lane_up<2>(c0); o1 = lane_up<2>(c1); o2 = lane_up<2>(c2); oa = lane_up<2>(a);
             } else if (d == 4) {
                 o0 = lane_up<4>(c0); o1 = lane_up<4>(c1); o2 = lane_up<4>(c2); oa = lane_up<4>(a);
-            } else if (d == 8) {
-                o0 = lane_up<8>(c0); o1 = lane_up<8>(c1); o2 = lane_up<8>(c2); oa = lane_up<8>(a);
-            } else if (d == 16) {
-                o0 = lane_up<16>(c0); o1 = lane_up<16>(c1); o2 = lane_up<16>(c2); oa = lane_up<16>(a);
             } else {
-                o0 = lane_up<32>(c0); o1 = lane_up<32>(c1); o2 = lane_up<32>(c2); oa = lane_up<32>(a);
+                o0 = lane_up<8>(c0); o1 = lane_up<8>(c1); o2 = lane_up<8>(c2); oa = lane_up<8>(a);
             }
-            if (g >= d) {
+            if ((g & 15) >= d) {
+                const float t = 1.f - oa;
+                c0 = fmaf(t, c0, o0);
+                c1 = fmaf(t, c1, o1);
+                c2 = fmaf(t, c2, o2);
+                a = fmaf(t, a, oa);
+            }
+        }
+        // ... then each row appends the total of the rows before it in its group
+        // (the last lane of the row below, after that row's own update)
+#pragma unroll
+        for (int r = 16; r < G; r <<= 1) {
+            const int src = (lane & ~(2 * r - 1)) + r - 1;
+            const float o0 = __shfl(c0, src, 64), o1 = __shfl(c1, src, 64), o2 = __shfl(c2, src, 64);
+            const float oa = __shfl(a, src, 64);
+            if (g & r) {
                 const float t = 1.f - oa;
                 c0 = fmaf(t, c0, o0);
                 c1 = fmaf(t, c1, o1);
@@ -995,17 +1002,29 @@ __global__ void derive_kernel(DeriveArgs a) {
         const int x = (int)(i % ex) - a.g;
         const int y = (int)((i / ex) % ey) - a.g;
         const int z = (int)(i / (ex * ey)) - a.g;
-        for (int s = 0; s < a.n; ++s) {
-            const DevSource& S = a.src[s];
-            // a source without guard layers never has them read: its guard cells hold the border values
-            const int qx = S.guard < 1 ? clampi(x, 0, a.ext[0] - 2 * a.g - 1) : x;
-            const int qy = S.guard < 1 ? clampi(y, 0, a.ext[1] - 2 * a.g - 1) : y;
-            const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
-            const int off[1] = {qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2]};
-            float v[1][4], r[1];
-            fetch<1>(S, off, v);
-            run_chain<1>(S, v, r);
-            a.dst[i * a.n + s] = r[0];
+        float out[kMaxDerived] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < kMaxDerived; ++s) {
+            if (s < a.n) {
+                const DevSource& S = a.src[s];
+                // a source without guard layers never has them read: its guard cells hold the border values
+                const int qx = S.guard < 1 ? clampi(x, 0, a.ext[0] - 2 * a.g - 1) : x;
+                const int qy = S.guard < 1 ? clampi(y, 0, a.ext[1] - 2 * a.g - 1) : y;
+                const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
+                const int off[1] = {qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2]};
+                float v[1][4], r[1];
+                fetch<1>(S, off, v);
+                run_chain<1>(S, v, r);
+                out[s] = r[0];
+            }
+        }
+        // one contiguous store per voxel
+        float* d = a.dst + i * a.n;
+        switch (a.n) {
+        case 4: *reinterpret_cast<float4*>(d) = make_float4(out[0], out[1], out[2], out[3]); break;
+        case 3: d[0] = out[0]; d[1] = out[1]; d[2] = out[2]; break;
+        case 2: d[0] = out[0]; d[1] = out[1]; break;
+        default: d[0] = out[0]; break;
         }
     }
 }
