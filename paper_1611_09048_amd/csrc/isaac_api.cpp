@@ -935,6 +935,36 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
             if (jobs[i].volume_id != vid) continue;
             for (int k = 0; k < djs[i].n_src; ++k) da.src[comp_of[djs[i].src_index[k]]] = djs[i].src[k];
         }
+        // voxels clipped away for every job of the volume are never read: skip them
+        // (up to kMaxKeepSets jobs; a job without planes needs every voxel)
+        int sets = 0;
+        bool all_voxels = false;
+        for (int i = 0; i < n && !all_voxels; ++i) {
+            if (jobs[i].volume_id != vid) continue;
+            const DevJob& dj = djs[i];
+            bool same_org = true;
+            for (int i0 = 0; i0 < i; ++i0)
+                if (jobs[i0].volume_id == vid)
+                    for (int a = 0; a < 3; ++a) same_org = same_org && djs[i0].org[a] == dj.org[a];
+            if (dj.n_clip == 0 || sets == kMaxKeepSets || !same_org) {
+                all_voxels = true;
+                break;
+            }
+            da.n_planes[sets] = dj.n_clip;
+            for (int c = 0; c < dj.n_clip; ++c) {
+                const double* pl = dj.clip[c];
+                const double nl = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+                for (int e = 0; e < 4; ++e) da.planes[sets][c][e] = (float)(pl[e] / nl);
+            }
+            ++sets;
+        }
+        da.n_sets = all_voxels ? 0 : sets;
+        for (int a = 0; a < 3; ++a) da.org[a] = djs[0].org[a];
+        for (int i = 0; i < n; ++i)
+            if (jobs[i].volume_id == vid) {
+                for (int a = 0; a < 3; ++a) da.org[a] = djs[i].org[a];
+                break;
+            }
         int rc = launch_derive(da, stream);
         if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "derive launch: %s", hipGetErrorString((hipError_t)rc));
         const int32_t sx = 4 * nd, sy = (int32_t)(sx * ex), sz = (int32_t)(sy * ey);

@@ -128,11 +128,19 @@ int raycast_occupancy(int* blocks_per_cu);
 // Derived volume: the functor-chain output of up to 4 sources at every voxel
 // of [-g, N-1+g]^3, interleaved (n floats per voxel, x fastest).
 constexpr int kMaxDerived = 4;
+constexpr int kMaxKeepSets = 4;
 struct DeriveArgs {
     DevSource src[kMaxDerived];   // as the ray loop would read them
     int n;                        // sources (components per voxel)
     int g;                        // guard layers covered
     int ext[3];                   // N + 2g per axis
+    float org[3];                 // index of voxel (0,0,0) in the clip planes' space
+    // Voxels no kept scan point can read are skipped: a voxel is derived if,
+    // for at least one set, it lies within 3 voxels of every plane's kept side
+    // (normalized planes; n_sets = 0: derive every voxel).
+    int n_sets;
+    int n_planes[kMaxKeepSets];
+    float planes[kMaxKeepSets][kMaxClip][4];
     float* dst;
 };
 int launch_derive(const DeriveArgs& a, void* stream);

@@ -1002,7 +1002,24 @@ __global__ void derive_kernel(DeriveArgs a) {
         const int x = (int)(i % ex) - a.g;
         const int y = (int)((i / ex) % ey) - a.g;
         const int z = (int)(i / (ex * ey)) - a.g;
-        float out[kMaxDerived] = {0.f, 0.f, 0.f, 0.f};
+        if (a.n_sets > 0) {
+            // a kept scan point reads voxel centres less than one voxel away per axis
+            // (1.5 for the iso-surface gradient), i.e. within 1.5 sqrt(3) < 3 of it
+            // along any unit normal
+            const float c[3] = {a.org[0] + x + 0.5f, a.org[1] + y + 0.5f, a.org[2] + z + 0.5f};
+            bool needed = false;
+            for (int k = 0; k < a.n_sets && !needed; ++k) {
+                bool inside = true;
+                for (int p = 0; p < a.n_planes[k]; ++p) {
+                    const float* pl = a.planes[k][p];
+                    inside = inside && pl[0] * c[0] + pl[1] * c[1] + pl[2] * c[2] + pl[3] >= -3.f;
+                }
+                needed = inside;
+            }
+            if (!needed) continue;
+        }
+        // every source's loads first, then the chains
+        float v[kMaxDerived][1][4];
 #pragma unroll
         for (int s = 0; s < kMaxDerived; ++s) {
             if (s < a.n) {
@@ -1012,9 +1029,15 @@ __global__ void derive_kernel(DeriveArgs a) {
                 const int qy = S.guard < 1 ? clampi(y, 0, a.ext[1] - 2 * a.g - 1) : y;
                 const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
                 const int off[1] = {qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2]};
-                float v[1][4], r[1];
-                fetch<1>(S, off, v);
-                run_chain<1>(S, v, r);
+                fetch<1>(S, off, v[s]);
+            }
+        }
+        float out[kMaxDerived] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < kMaxDerived; ++s) {
+            if (s < a.n) {
+                float r[1];
+                run_chain<1>(a.src[s], v[s], r);
                 out[s] = r[0];
             }
         }

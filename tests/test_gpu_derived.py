@@ -91,18 +91,21 @@ def test_derived_iso_mode(ctx):
 
 
 def test_derived_batch_of_views(ctx):
-    """Several jobs on one volume with different enabled sets share one derived volume."""
+    """Several jobs on one volume with different enabled sets and clip planes share
+    one derived volume; voxels clipped away for every job are not derived."""
     import torch
     from paper_1611_09048_amd import DERIVE, DIRECT, device
     sc = configs.pic3(n=40, width=112, height=80)
     vol = device.upload_volume(ctx, sc, 6)
     views = [configs.D0, (0.2, -0.9, 0.4), (-0.7, -0.1, -0.7)]
     enabled = [None, [True, False, True], [False, True, True]]
+    rng = np.random.default_rng(21)
+    clips = [[configs.random_clip_plane(rng, sc.dims) for _ in range(k)] for k in (1, 3, 2)]
     out = {}
     for flags in (DIRECT, DERIVE):
         imgs = [device.new_image(sc) for _ in views]
-        jobs = [device.render_job(sc.with_(camera=configs.orbit_camera(sc.dims, v)), 6, im, enabled=e)
-                for v, im, e in zip(views, imgs, enabled)]
+        jobs = [device.render_job(sc.with_(camera=configs.orbit_camera(sc.dims, v), clip=c), 6, im, enabled=e)
+                for v, im, e, c in zip(views, imgs, enabled, clips)]
         for _ in range(3):                      # graph replays included
             ctx.render(jobs, flags)
         torch.cuda.synchronize()
@@ -110,3 +113,20 @@ def test_derived_batch_of_views(ctx):
     for k in range(len(views)):
         assert np.array_equal(out[DIRECT][k], out[DERIVE][k]), k
     del vol
+
+
+def test_derived_skips_clipped_voxels_only(ctx):
+    """Clip planes cutting most of the volume away, in volume and iso mode, nearest
+    and trilinear: the skipped voxels are never read (derived equals direct)."""
+    base = configs.pic3(n=40, width=128, height=96, direction=(0.5, 0.6, -0.6))
+    c = np.array(base.dims, dtype=np.float64) / 2
+    for k, (normal, off) in enumerate((((1.0, 0.2, 0.1), 6.0), ((-0.3, 1.0, 0.4), -3.0), ((0.0, 0.0, 1.0), 12.0))):
+        nrm = np.array(normal) / np.linalg.norm(normal)
+        plane = (float(nrm[0]), float(nrm[1]), float(nrm[2]), float(-(nrm @ c) - off))
+        sc = base.with_(clip=[plane], interpolation=k % 2)
+        a, b = both(ctx, sc, vid=7)
+        assert_same(a, b, f"heavy clip {k}")
+    iso = base.with_(clip=[plane], mode="iso",
+                     sources=[dataclasses.replace(s, iso=v) for s, v in zip(base.sources, (1.0, 0.2, float("nan")))])
+    a, b = both(ctx, iso, vid=8)
+    assert_same(a, b, "heavy clip iso")
