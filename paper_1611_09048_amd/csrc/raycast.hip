@@ -994,14 +994,16 @@ __global__ void encode_rgba8_kernel(EncodeArgs a) {
 // Derived volume: every voxel's chain output per source, computed once with
 // the same fetch and chain code as the ray loop (so the values are the ones
 // the loop would compute at that voxel, bit for bit).  One thread per voxel,
-// x fastest: reads and the interleaved writes are coalesced.
-__global__ void derive_kernel(DeriveArgs a) {
-    const int64_t ex = a.ext[0], ey = a.ext[1];
-    const int64_t n = ex * ey * a.ext[2];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % ex) - a.g;
-        const int y = (int)((i / ex) % ey) - a.g;
-        const int z = (int)(i / (ex * ey)) - a.g;
+// x fastest: reads and the interleaved writes are coalesced.  A 3-D grid
+// (64 x 4 threads per block over x and y, blocks over z) needs no index
+// division.
+__global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
+    const int xi = (int)(blockIdx.x * 64 + threadIdx.x);
+    const int yi = (int)(blockIdx.y * 4 + threadIdx.y);
+    if (xi >= a.ext[0] || yi >= a.ext[1]) return;
+    for (int zi = (int)blockIdx.z; zi < a.ext[2]; zi += (int)gridDim.z) {
+        const int64_t i = ((int64_t)zi * a.ext[1] + yi) * a.ext[0] + xi;
+        const int x = xi - a.g, y = yi - a.g, z = zi - a.g;
         if (a.n_sets > 0) {
             // a kept scan point reads voxel centres less than one voxel away per axis
             // (1.5 for the iso-surface gradient), i.e. within 1.5 sqrt(3) < 3 of it
@@ -1067,12 +1069,14 @@ struct CopyArgs {
     int lo[3], ext[3];
 };
 
-__global__ void strided_copy_kernel(CopyArgs a) {
-    const int64_t n = (int64_t)a.ext[0] * a.ext[1] * a.ext[2];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % a.ext[0]) + a.lo[0];
-        const int y = (int)((i / a.ext[0]) % a.ext[1]) + a.lo[1];
-        const int z = (int)(i / ((int64_t)a.ext[0] * a.ext[1])) + a.lo[2];
+__global__ __launch_bounds__(256) void strided_copy_kernel(CopyArgs a) {
+    const int xi = (int)(blockIdx.x * 64 + threadIdx.x);
+    const int yi = (int)(blockIdx.y * 4 + threadIdx.y);
+    if (xi >= a.ext[0] || yi >= a.ext[1]) return;
+    for (int zi = (int)blockIdx.z; zi < a.ext[2]; zi += (int)gridDim.z) {
+        const int x = xi + a.lo[0];
+        const int y = yi + a.lo[1];
+        const int z = zi + a.lo[2];
         for (int c = 0; c < a.f_dim; ++c) {
             const unsigned char* s = a.src[c] + x * a.src_stride[0] + y * a.src_stride[1] + z * a.src_stride[2];
             unsigned char* d = a.dst + x * a.dst_stride[0] + y * a.dst_stride[1] + z * a.dst_stride[2] +
@@ -1154,11 +1158,9 @@ int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, 
     a.dst = static_cast<unsigned char*>(dst);
     a.esize = esize;
     a.f_dim = f_dim;
-    const int64_t n = (int64_t)ext[0] * ext[1] * ext[2];
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(strided_copy_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0,
-                       (hipStream_t)stream, a);
+    if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((ext[0] + 63) / 64), (unsigned)((ext[1] + 3) / 4), (unsigned)std::min(ext[2], 65535));
+    hipLaunchKernelGGL(strided_copy_kernel, grid, dim3(64, 4), 0, (hipStream_t)stream, a);
     return hipGetLastError();
 }
 
@@ -1193,10 +1195,10 @@ int launch_encode_rgba8(const float* rgba, int64_t n_pixels, const float* bg, un
 }
 
 int launch_derive(const DeriveArgs& a, void* stream) {
-    const int64_t n = (int64_t)a.ext[0] * a.ext[1] * a.ext[2];
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
-    if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(derive_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
+    if (a.ext[0] <= 0 || a.ext[1] <= 0 || a.ext[2] <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.ext[0] + 63) / 64), (unsigned)((a.ext[1] + 3) / 4),
+                    (unsigned)std::min(a.ext[2], 65535));
+    hipLaunchKernelGGL(derive_kernel, grid, dim3(64, 4), 0, (hipStream_t)stream, a);
     return hipGetLastError();
 }
 
