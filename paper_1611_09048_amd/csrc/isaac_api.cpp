@@ -965,7 +965,13 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
                 for (int a = 0; a < 3; ++a) da.org[a] = djs[i].org[a];
                 break;
             }
-        int rc = launch_derive(da, stream);
+        // the sources' own signature selects a compile-time specialized derive
+        DevJob probe;
+        std::memset(&probe, 0, sizeof probe);
+        probe.n_src = nd;
+        for (int k = 0; k < nd; ++k) probe.src[k] = da.src[k];
+        const int dsig = signature_of(probe);
+        int rc = launch_derive(da, dsig == SIG_IL3 ? (int)SIG_GENERIC : dsig, stream);
         if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "derive launch: %s", hipGetErrorString((hipError_t)rc));
         const int32_t sx = 4 * nd, sy = (int32_t)(sx * ex), sz = (int32_t)(sy * ey);
         const int32_t o0 = g * (sx + sy + sz);

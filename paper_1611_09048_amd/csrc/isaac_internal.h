@@ -143,7 +143,8 @@ struct DeriveArgs {
     float planes[kMaxKeepSets][kMaxClip][4];
     float* dst;
 };
-int launch_derive(const DeriveArgs& a, void* stream);
+// sig: the Signature of src[0..n) (their compile-time kinds), or SIG_GENERIC
+int launch_derive(const DeriveArgs& a, int sig, void* stream);
 constexpr int kMaxLayers = 16;
 int launch_composite(const float* const* rgba, const float* const* depth, int n_layers, int64_t n_pixels,
                      float* out, void* stream);

@@ -993,16 +993,19 @@ __global__ void encode_rgba8_kernel(EncodeArgs a) {
 
 // Derived volume: every voxel's chain output per source, computed once with
 // the same fetch and chain code as the ray loop (so the values are the ones
-// the loop would compute at that voxel, bit for bit).  One thread per voxel,
-// x fastest: reads and the interleaved writes are coalesced.  A 3-D grid
-// (64 x 4 threads per block over x and y, blocks over z) needs no index
-// division.
+// the loop would compute at that voxel, bit for bit).  Blocks of 256 threads
+// cover consecutive voxels of one z-slice (x fastest): reads and the
+// interleaved writes are coalesced.  SIG > 0: the sources have that
+// signature's compile-time kinds; SIG = 0: any sources.
+template <int SIG>
 __global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
-    const int xi = (int)(blockIdx.x * 64 + threadIdx.x);
-    const int yi = (int)(blockIdx.y * 4 + threadIdx.y);
-    if (xi >= a.ext[0] || yi >= a.ext[1]) return;
+    const int ex = a.ext[0], ey = a.ext[1];
+    const int idx = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (idx >= ex * ey) return;
+    const int yi = idx / ex;
+    const int xi = idx - yi * ex;
     for (int zi = (int)blockIdx.z; zi < a.ext[2]; zi += (int)gridDim.z) {
-        const int64_t i = ((int64_t)zi * a.ext[1] + yi) * a.ext[0] + xi;
+        const int64_t i = (int64_t)zi * ex * ey + idx;
         const int x = xi - a.g, y = yi - a.g, z = zi - a.g;
         if (a.n_sets > 0) {
             // a kept scan point reads voxel centres less than one voxel away per axis
@@ -1020,27 +1023,55 @@ __global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
             }
             if (!needed) continue;
         }
-        // every source's loads first, then the chains
-        float v[kMaxDerived][1][4];
-#pragma unroll
-        for (int s = 0; s < kMaxDerived; ++s) {
-            if (s < a.n) {
-                const DevSource& S = a.src[s];
-                // a source without guard layers never has them read: its guard cells hold the border values
-                const int qx = S.guard < 1 ? clampi(x, 0, a.ext[0] - 2 * a.g - 1) : x;
-                const int qy = S.guard < 1 ? clampi(y, 0, a.ext[1] - 2 * a.g - 1) : y;
-                const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
-                const int off[1] = {qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2]};
-                fetch<1>(S, off, v[s]);
-            }
-        }
+        // a source without guard layers never has them read: its guard cells hold the border values
+        auto offset = [&](const DevSource& S) {
+            const int qx = S.guard < 1 ? clampi(x, 0, ex - 2 * a.g - 1) : x;
+            const int qy = S.guard < 1 ? clampi(y, 0, ey - 2 * a.g - 1) : y;
+            const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
+            return qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2];
+        };
         float out[kMaxDerived] = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (SIG == SIG_GENERIC) {
+            // every source's loads first, then the chains
+            float v[kMaxDerived][1][4];
 #pragma unroll
-        for (int s = 0; s < kMaxDerived; ++s) {
-            if (s < a.n) {
-                float r[1];
-                run_chain<1>(a.src[s], v[s], r);
-                out[s] = r[0];
+            for (int s = 0; s < kMaxDerived; ++s) {
+                if (s < a.n) {
+                    const int off[1] = {offset(a.src[s])};
+                    fetch<1>(a.src[s], off, v[s]);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < kMaxDerived; ++s) {
+                if (s < a.n) {
+                    float r[1];
+                    run_chain<1>(a.src[s], v[s], r);
+                    out[s] = r[0];
+                }
+            }
+        } else {
+            constexpr int K0 = SigKinds<SIG>::k0, K1 = SigKinds<SIG>::k1, K2 = SigKinds<SIG>::k2;
+            float v0[1][4], v1[1][4], v2[1][4];
+            const int o0[1] = {offset(a.src[0])};
+            fetch_kind<K0, 1>(a.src[0], o0, v0);
+            if constexpr (K1 != K_NONE) {
+                const int o1[1] = {offset(a.src[1])};
+                fetch_kind<K1, 1>(a.src[1], o1, v1);
+            }
+            if constexpr (K2 != K_NONE) {
+                const int o2[1] = {offset(a.src[2])};
+                fetch_kind<K2, 1>(a.src[2], o2, v2);
+            }
+            float r[1];
+            run_chain<1, KindOf<K0>::dim>(a.src[0], v0, r);
+            out[0] = r[0];
+            if constexpr (K1 != K_NONE) {
+                run_chain<1, KindOf<K1>::dim>(a.src[1], v1, r);
+                out[1] = r[0];
+            }
+            if constexpr (K2 != K_NONE) {
+                run_chain<1, KindOf<K2>::dim>(a.src[2], v2, r);
+                out[2] = r[0];
             }
         }
         // one contiguous store per voxel
@@ -1194,11 +1225,20 @@ int launch_encode_rgba8(const float* rgba, int64_t n_pixels, const float* bg, un
     return hipGetLastError();
 }
 
-int launch_derive(const DeriveArgs& a, void* stream) {
+int launch_derive(const DeriveArgs& a, int sig, void* stream) {
     if (a.ext[0] <= 0 || a.ext[1] <= 0 || a.ext[2] <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.ext[0] + 63) / 64), (unsigned)((a.ext[1] + 3) / 4),
-                    (unsigned)std::min(a.ext[2], 65535));
-    hipLaunchKernelGGL(derive_kernel, grid, dim3(64, 4), 0, (hipStream_t)stream, a);
+    const int64_t slice = (int64_t)a.ext[0] * a.ext[1];
+    if (slice > (1LL << 30)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((slice + 255) / 256), 1, (unsigned)std::min(a.ext[2], 65535));
+    void (*k)(DeriveArgs) = derive_kernel<SIG_GENERIC>;
+    switch (sig) {
+    case SIG_F32x1: k = derive_kernel<SIG_F32x1>; break;
+    case SIG_PIC3_F32: k = derive_kernel<SIG_PIC3_F32>; break;
+    case SIG_PIC3_F16: k = derive_kernel<SIG_PIC3_F16>; break;
+    case SIG_PIC3_BF16: k = derive_kernel<SIG_PIC3_BF16>; break;
+    default: break;
+    }
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, (hipStream_t)stream, a);
     return hipGetLastError();
 }
 
