@@ -245,17 +245,23 @@ isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count);
  *     are issued together;
  *   min_waves in {0,4}: 4 selects the kernel variant compiled to keep at
  *     least 4 waves resident per SIMD (not with lanes_per_ray 2, 32, 64 or
- *     unroll 2).
+ *     unroll 2);
+ *   pooled in {0,1} (lanes_per_ray 2..16): a render call's single-job
+ *     launches first set up every pixel's ray and compact the rays that keep
+ *     scan points into a list, then resident waves hand those rays to lane
+ *     groups as groups free up (no lanes idle on short or missing rays).
+ *     Only isaac_render uses it (a library-owned list of 40 bytes per pixel,
+ *     kept in the context); serving and batched launches use the tiles.
  * A batch runs one launch per distinct schedule, so each job is rendered as
  * it would be alone.
- * Defaults: (8, 2, 1, 1, 0).  Settings with one lane per ray give the same
+ * Defaults: (8, 2, 1, 1, 0, 0).  Settings with one lane per ray give the same
  * image bit for bit; more lanes composite each row of scan points by a scan,
  * which changes only FP32 rounding; a given setting always reproduces its
  * image bit for bit. */
 isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w, int waves_x, int unroll,
-                                  int lanes_per_ray, int min_waves);
+                                  int lanes_per_ray, int min_waves, int pooled);
 isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_w, int* waves_x, int* unroll,
-                                  int* lanes_per_ray, int* min_waves);
+                                  int* lanes_per_ray, int* min_waves, int* pooled);
 
 /* ---- serving: library-owned output images admitted against mem_budget ---- */
 

@@ -25,7 +25,8 @@ WAVES_X = (1, 2, 4)
 UNROLL = (1, 2)
 LANES = (1, 2, 4, 8, 16, 32, 64)
 MIN_WAVES = (0, 4)
-DEFAULT = (8, 2, 1, 1, 0)
+POOLED = (0, 1)
+DEFAULT = (8, 2, 1, 1, 0, 0)
 
 
 def size_class(width: int, height: int) -> int:
@@ -34,18 +35,24 @@ def size_class(width: int, height: int) -> int:
 
 
 def candidates(unrolls: Sequence[int] = UNROLL, lanes: Sequence[int] = LANES, wave_ws: Sequence[int] = WAVE_W,
-               waves_xs: Sequence[int] = WAVES_X, min_waves: Sequence[int] = MIN_WAVES) -> List[Tuple]:
-    """Valid (wave_w, waves_x, unroll, lanes_per_ray, min_waves) settings."""
+               waves_xs: Sequence[int] = WAVES_X, min_waves: Sequence[int] = MIN_WAVES,
+               pooled: Sequence[int] = POOLED) -> List[Tuple]:
+    """Valid (wave_w, waves_x, unroll, lanes_per_ray, min_waves, pooled) settings.
+
+    The pooled schedule ignores the tile shape, so it is tried once per lane count."""
     out = []
     for g in lanes:
         for u in (unrolls if g == 1 else (1,)):
             for m in min_waves:
                 if m and (g == 2 or g >= 32 or u == 2):
                     continue
-                for w in wave_ws:
-                    if w <= 64 // g and (w >= 8 or w == 64 // g):
-                        for x in waves_xs:
-                            out.append((w, x, u, g, m))
+                if 0 in pooled:
+                    for w in wave_ws:
+                        if w <= 64 // g and (w >= 8 or w == 64 // g):
+                            for x in waves_xs:
+                                out.append((w, x, u, g, m, 0))
+                if 1 in pooled and 2 <= g <= 16 and u == 1:
+                    out.append((min(8, 64 // g), 2, 1, g, m, 1))
     return out
 
 

@@ -109,8 +109,8 @@ def load(path: Optional[str] = None):
     lib.isaac_encode_rgba8.argtypes = [c_ctx, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_uint]
     lib.isaac_read_image_rgba8.argtypes = [c_ctx, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
-    lib.isaac_set_tile_shape.argtypes = [c_ctx] + [ctypes.c_int] * 6
-    lib.isaac_get_tile_shape.argtypes = [c_ctx, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 5
+    lib.isaac_set_tile_shape.argtypes = [c_ctx] + [ctypes.c_int] * 7
+    lib.isaac_get_tile_shape.argtypes = [c_ctx, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 6
     lib.isaac_submit.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.POINTER(ctypes.c_uint64)]
     lib.isaac_submit_batch.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_uint64)]
@@ -224,11 +224,12 @@ class Context:
         return ms.value, n.value
 
     def set_tile_shape(self, size_class: int, wave_w: int, waves_x: int, unroll: int = 1, lanes: int = 1,
-                       min_waves: int = 0):
-        self._check(self.lib.isaac_set_tile_shape(self.h, size_class, wave_w, waves_x, unroll, lanes, min_waves))
+                       min_waves: int = 0, pooled: int = 0):
+        self._check(self.lib.isaac_set_tile_shape(self.h, size_class, wave_w, waves_x, unroll, lanes, min_waves,
+                                                  pooled))
 
     def get_tile_shape(self, size_class: int):
-        v = [ctypes.c_int() for _ in range(5)]
+        v = [ctypes.c_int() for _ in range(6)]
         self._check(self.lib.isaac_get_tile_shape(self.h, size_class, *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 

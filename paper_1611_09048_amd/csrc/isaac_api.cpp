@@ -248,7 +248,7 @@ struct Ticket {
 };
 
 struct TileShape {
-    int wave_w = 8, waves_x = 2, unroll = 1, lanes = 1, waves_hint = 0;
+    int wave_w = 8, waves_x = 2, unroll = 1, lanes = 1, waves_hint = 0, pool = 0;
 };
 
 }  // namespace
@@ -285,6 +285,9 @@ struct isaac_context {
     uint64_t next_ticket = 1;
     void* enc_buf = nullptr;           // RGBA8 staging of isaac_read_image_rgba8
     size_t enc_bytes = 0;
+    void* pool_rays = nullptr;         // compacted rays of the pooled schedule
+    size_t pool_bytes = 0;
+    int* pool_counters = nullptr;      // [appended rays, handed-out rays]
     TileShape shapes[16];
     std::string last_error;
     bool sticky = false;
@@ -647,6 +650,7 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
     dj.unroll = ts.unroll;
     dj.lanes = ts.lanes;
     dj.waves_hint = ts.waves_hint;
+    dj.pool = ts.pool;
     set_tiles(dj, ts.lanes, ts.unroll);
     dj.out = j.out_rgba;
     dj.out_samples = j.out_samples;
@@ -750,8 +754,29 @@ isaac_status acquire_slot(isaac_context* ctx, RingSlot** out) {
     return ISAAC_OK;
 }
 
+// Ray buffer and counters of the pooled schedule, grown to `bytes`.
+bool ensure_pool(isaac_context* ctx, size_t bytes, hipStream_t stream) {
+    if (!ctx->pool_counters && hipMalloc(&ctx->pool_counters, 2 * sizeof(int)) != hipSuccess) {
+        ctx->pool_counters = nullptr;
+        return false;
+    }
+    if (bytes <= ctx->pool_bytes) return true;
+    if (ctx->pool_rays) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return false;
+        hipFree(ctx->pool_rays);
+    }
+    ctx->pool_rays = nullptr;
+    ctx->pool_bytes = 0;
+    if (hipMalloc(&ctx->pool_rays, bytes) != hipSuccess) {
+        ctx->pool_rays = nullptr;
+        return false;
+    }
+    ctx->pool_bytes = bytes;
+    return true;
+}
+
 isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, const std::vector<DevJob>& djs,
-                          int max_src, unsigned flags, hipStream_t stream) {
+                          int max_src, unsigned flags, hipStream_t stream, bool allow_pool) {
     const int n = (int)djs.size();
     RingSlot* r = nullptr;
     isaac_status st = acquire_slot(ctx, &r);
@@ -831,6 +856,16 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
         }
         if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
         HIP_TRY(ctx, hipGraphLaunch(r->exec, stream));
+        if (t1) HIP_TRY(ctx, hipEventRecord(t1, stream));
+    } else if (n == 1 && allow_pool && djs[0].pool && lanes >= 2 && lanes <= 16 && djs[0].mode == ISAAC_VOLUME &&
+               (size_t)djs[0].width * djs[0].height * ray_record_bytes() < ((size_t)1 << 31) &&
+               ensure_pool(ctx, (size_t)djs[0].width * djs[0].height * ray_record_bytes(), stream)) {
+        // pooled schedule: compacted rays handed to lane groups as they free up
+        HIP_TRY(ctx, hipMemcpyAsync(r->dev, r->host, sizeof(DevJob), hipMemcpyHostToDevice, stream));
+        if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
+        int rc = launch_raycast_pooled(r->dev, djs[0].width, djs[0].height, ctx->tf_pool, la.max_src, la.sig, lanes,
+                                       la.waves_hint, ctx->pool_rays, ctx->pool_counters, ctx->n_cu, stream);
+        if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "raycast launch: %s", hipGetErrorString((hipError_t)rc));
         if (t1) HIP_TRY(ctx, hipEventRecord(t1, stream));
     } else {
         HIP_TRY(ctx, hipMemcpyAsync(r->dev, r->host, sizeof(DevJob) * n, hipMemcpyHostToDevice, stream));
@@ -1045,7 +1080,7 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
     std::vector<std::vector<DevJob>> groups;
     std::vector<int> keys;
     for (const DevJob& dj : djs) {
-        const int key = dj.mode * 1024 + dj.lanes * 16 + dj.unroll * 2 + dj.waves_hint;
+        const int key = dj.mode * 2048 + dj.pool * 1024 + dj.lanes * 16 + dj.unroll * 2 + dj.waves_hint;
         size_t g = 0;
         while (g < keys.size() && keys[g] != key) ++g;
         if (g == keys.size()) {
@@ -1057,7 +1092,7 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
     for (const auto& grp : groups) {
         int ms = 1;
         for (const DevJob& dj : grp) ms = std::max(ms, (int)dj.n_src);
-        st = enqueue_jobs(ctx, jobs, grp, ms, flags, stream);
+        st = enqueue_jobs(ctx, jobs, grp, ms, flags, stream, allow_derive);
         if (st) return st;
     }
     (void)max_src;
@@ -1197,6 +1232,8 @@ void isaac_destroy(isaac_context* ctx) {
     for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
     if (ctx->tf_pool) hipFree(ctx->tf_pool);
     if (ctx->enc_buf) hipFree(ctx->enc_buf);
+    if (ctx->pool_rays) hipFree(ctx->pool_rays);
+    if (ctx->pool_counters) hipFree(ctx->pool_counters);
     for (hipStream_t s : ctx->serve_streams) hipStreamDestroy(s);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
@@ -1378,21 +1415,22 @@ isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count) {
 }
 
 isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w, int waves_x, int unroll,
-                                  int lanes_per_ray, int min_waves) {
+                                  int lanes_per_ray, int min_waves, int pooled) {
     if (!ctx) return ISAAC_ERR_INVALID_ARGUMENT;
     const int g = lanes_per_ray;
     const bool lanes_ok = g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64;
     const bool ww_ok = wave_w >= 1 && wave_w <= 64 && (wave_w & (wave_w - 1)) == 0 && lanes_ok && wave_w <= 64 / g;
     if (size_class < 0 || size_class > 15 || !ww_ok || (waves_x != 1 && waves_x != 2 && waves_x != 4) ||
         (unroll != 1 && unroll != 2) || (g > 1 && unroll != 1) || (min_waves != 0 && min_waves != 4) ||
-        (min_waves == 4 && (g == 2 || g >= 32 || unroll == 2)))
+        (min_waves == 4 && (g == 2 || g >= 32 || unroll == 2)) || (pooled != 0 && pooled != 1) ||
+        (pooled == 1 && (g < 2 || g > 16)))
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "invalid tile shape");
-    ctx->shapes[size_class] = TileShape{wave_w, waves_x, unroll, g, min_waves == 4 ? 1 : 0};
+    ctx->shapes[size_class] = TileShape{wave_w, waves_x, unroll, g, min_waves == 4 ? 1 : 0, pooled};
     return ISAAC_OK;
 }
 
 isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_w, int* waves_x, int* unroll,
-                                  int* lanes_per_ray, int* min_waves) {
+                                  int* lanes_per_ray, int* min_waves, int* pooled) {
     if (!ctx || size_class < 0 || size_class > 15) return ISAAC_ERR_INVALID_ARGUMENT;
     const TileShape& t = ctx->shapes[size_class];
     if (wave_w) *wave_w = t.wave_w;
@@ -1400,6 +1438,7 @@ isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_
     if (unroll) *unroll = t.unroll;
     if (lanes_per_ray) *lanes_per_ray = t.lanes;
     if (min_waves) *min_waves = t.waves_hint ? 4 : 0;
+    if (pooled) *pooled = t.pool;
     return ISAAC_OK;
 }
 

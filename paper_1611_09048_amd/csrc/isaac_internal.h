@@ -91,6 +91,7 @@ struct DevJob {
     int32_t waves_hint;    // 1: run the variant compiled for at least 4 waves per SIMD
     int32_t sig;           // Signature of the active sources
     int32_t mode;          // 0 volume compositing, 1 first iso-surface
+    int32_t pool;          // 1: pooled schedule requested (single-job launches with lanes >= 2)
     int32_t tiles_x, tiles_y;
     int32_t tile_begin;    // first tile index of this job in the batch
     int32_t cull[4];       // pixels [cull[0], cull[2]] x [cull[1], cull[3]] hold every ray that can meet the box
@@ -120,6 +121,12 @@ struct LaunchArgs {
 
 int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t
 int launch_reset_counter(int* counter, void* stream);
+// Pooled schedule of one job (lanes >= 2): ray setup with compaction into
+// `rays` (ray_record_bytes() per pixel), then a resident kernel handing the
+// compacted rays to lane groups.  counters: 2 device ints.
+int launch_raycast_pooled(const DevJob* job_dev, int width, int height, const float* tf_pool, int max_src, int sig,
+                          int lanes, int hint, void* rays, int* counters, int n_cu, void* stream);
+size_t ray_record_bytes();
 int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, void* dst,
                         const int64_t* dst_stride, int esize, int f_dim, const int32_t lo[3],
                         const int32_t ext[3], void* stream);

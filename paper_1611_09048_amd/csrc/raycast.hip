@@ -663,77 +663,90 @@ __device__ __forceinline__ float lane_up(float x) {
 // A + (1-A) A') across the group, then appended to the ray's running state.
 // The first point whose cumulative opacity reaches ert ends the ray, exactly
 // where the one-lane loop would stop.
+// Running front-to-back state of one ray composited by a group of G lanes.
+struct RayAccum {
+    float C0, C1, C2, A;
+    int n;
+};
+
+// One row of the lanes-per-ray schedule: scan points k0 .. k0+G-1 (those
+// below R.ke), composited into acc.  Returns true when the ray is finished
+// (termination, or no scan point left).
+template <int INTERP, int G, int SIG, bool PS>
+__device__ __forceinline__ bool lanes_row(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                          int lane, int k0, RayAccum& acc) {
+    const int g = lane & (G - 1);
+    const int k = k0 + g;
+    const bool valid = k < R.ke;
+    float E[1][3], S[1];
+    points<INTERP, 1, SIG, PS>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
+    float c0 = valid ? E[0][0] : 0.f, c1 = valid ? E[0][1] : 0.f, c2 = valid ? E[0][2] : 0.f;
+    float a = valid ? S[0] : 0.f;
+    // inclusive scan inside each row of 16 lanes ...
+#pragma unroll
+    for (int d = 1; d < (G < 16 ? G : 16); d <<= 1) {
+        float o0, o1, o2, oa;
+        if (d == 1) {
+            o0 = lane_up<1>(c0); o1 = lane_up<1>(c1); o2 = lane_up<1>(c2); oa = lane_up<1>(a);
+        } else if (d == 2) {
+            o0 = lane_up<2>(c0); o1 = lane_up<2>(c1); o2 = lane_up<2>(c2); oa = lane_up<2>(a);
+        } else if (d == 4) {
+            o0 = lane_up<4>(c0); o1 = lane_up<4>(c1); o2 = lane_up<4>(c2); oa = lane_up<4>(a);
+        } else {
+            o0 = lane_up<8>(c0); o1 = lane_up<8>(c1); o2 = lane_up<8>(c2); oa = lane_up<8>(a);
+        }
+        if ((g & 15) >= d) {
+            const float t = 1.f - oa;
+            c0 = fmaf(t, c0, o0);
+            c1 = fmaf(t, c1, o1);
+            c2 = fmaf(t, c2, o2);
+            a = fmaf(t, a, oa);
+        }
+    }
+    // ... then each row appends the total of the rows before it in its group
+    // (the last lane of the row below, after that row's own update)
+#pragma unroll
+    for (int r = 16; r < G; r <<= 1) {
+        const int src = (lane & ~(2 * r - 1)) + r - 1;
+        const float o0 = __shfl(c0, src, 64), o1 = __shfl(c1, src, 64), o2 = __shfl(c2, src, 64);
+        const float oa = __shfl(a, src, 64);
+        if (g & r) {
+            const float t = 1.f - oa;
+            c0 = fmaf(t, c0, o0);
+            c1 = fmaf(t, c1, o1);
+            c2 = fmaf(t, c2, o2);
+            a = fmaf(t, a, oa);
+        }
+    }
+    const float T = 1.f - acc.A;
+    const float n0 = fmaf(T, c0, acc.C0), n1 = fmaf(T, c1, acc.C1), n2 = fmaf(T, c2, acc.C2), na = fmaf(T, a, acc.A);
+    const unsigned long long m = __ballot(valid && na >= J.ert);
+    constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull);
+    const unsigned long long bits = (m >> (lane & ~(G - 1))) & kGroupMask;
+    const bool stop = bits != 0;
+    const int sel = stop ? __builtin_ctzll(bits) : min(G, R.ke - k0) - 1;
+    acc.n += sel + 1;
+    acc.C0 = __shfl(n0, sel, G);
+    acc.C1 = __shfl(n1, sel, G);
+    acc.C2 = __shfl(n2, sel, G);
+    acc.A = __shfl(na, sel, G);
+    return stop || k0 + G >= R.ke;
+}
+
+// G lanes per ray: lane g evaluates scan points kb + g, kb + g + G, ...; each
+// row of G points is composited in order with an inclusive scan of the
+// associative front-to-back operator (C, A) o (C', A') = (C + (1-A) C',
+// A + (1-A) A') across the group, then appended to the ray's running state.
+// The first point whose cumulative opacity reaches ert ends the ray, exactly
+// where the one-lane loop would stop.
 template <int INTERP, int G, int SIG, bool PS>
 __device__ __forceinline__ void march_lanes(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                             int lane, float4& out, int& count) {
-    const int g = lane & (G - 1);
-    const float ert = J.ert;
-    float Cr = 0.f, Cg = 0.f, Cb = 0.f, A = 0.f;
-    int n = 0;
-    bool stop = false;
-    for (int k0 = R.kb; k0 < R.ke && !stop; k0 += G) {
-        const int k = k0 + g;
-        const bool valid = k < R.ke;
-        float E[1][3], S[1];
-        points<INTERP, 1, SIG, PS>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
-        float c0 = valid ? E[0][0] : 0.f, c1 = valid ? E[0][1] : 0.f, c2 = valid ? E[0][2] : 0.f;
-        float a = valid ? S[0] : 0.f;
-        // inclusive scan inside each row of 16 lanes ...
-#pragma unroll
-        for (int d = 1; d < (G < 16 ? G : 16); d <<= 1) {
-            float o0, o1, o2, oa;
-            if (d == 1) {
-                o0 = lane_up<1>(c0); o1 = lane_up<1>(c1); o2 = lane_up<1>(c2); oa = lane_up<1>(a);
-            } else if (d == 2) {
-                o0 = lane_up<2>(c0); o1 = lane_up<2>(c1); o2 = lane_up<2>(c2); oa = lane_up<2>(a);
-            } else if (d == 4) {
-                o0 = lane_up<4>(c0); o1 = lane_up<4>(c1); o2 = lane_up<4>(c2); oa = lane_up<4>(a);
-            } else {
-                o0 = lane_up<8>(c0); o1 = lane_up<8>(c1); o2 = lane_up<8>(c2); oa = lane_up<8>(a);
-            }
-            if ((g & 15) >= d) {
-                const float t = 1.f - oa;
-                c0 = fmaf(t, c0, o0);
-                c1 = fmaf(t, c1, o1);
-                c2 = fmaf(t, c2, o2);
-                a = fmaf(t, a, oa);
-            }
-        }
-        // ... then each row appends the total of the rows before it in its group
-        // (the last lane of the row below, after that row's own update)
-#pragma unroll
-        for (int r = 16; r < G; r <<= 1) {
-            const int src = (lane & ~(2 * r - 1)) + r - 1;
-            const float o0 = __shfl(c0, src, 64), o1 = __shfl(c1, src, 64), o2 = __shfl(c2, src, 64);
-            const float oa = __shfl(a, src, 64);
-            if (g & r) {
-                const float t = 1.f - oa;
-                c0 = fmaf(t, c0, o0);
-                c1 = fmaf(t, c1, o1);
-                c2 = fmaf(t, c2, o2);
-                a = fmaf(t, a, oa);
-            }
-        }
-        const float T = 1.f - A;
-        const float n0 = fmaf(T, c0, Cr), n1 = fmaf(T, c1, Cg), n2 = fmaf(T, c2, Cb), na = fmaf(T, a, A);
-        const unsigned long long m = __ballot(valid && na >= ert);
-        constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull);
-        const unsigned long long bits = (m >> (lane & ~(G - 1))) & kGroupMask;
-        int sel;
-        if (bits) {
-            sel = __builtin_ctzll(bits);
-            stop = true;
-        } else {
-            sel = min(G, R.ke - k0) - 1;
-        }
-        n += sel + 1;
-        Cr = __shfl(n0, sel, G);
-        Cg = __shfl(n1, sel, G);
-        Cb = __shfl(n2, sel, G);
-        A = __shfl(na, sel, G);
-    }
-    out = make_float4(Cr, Cg, Cb, A);
-    count = n;
+    RayAccum acc = {0.f, 0.f, 0.f, 0.f, 0};
+    for (int k0 = R.kb;; k0 += G)
+        if (lanes_row<INTERP, G, SIG, PS>(J, s_tf, R, lane, k0, acc)) break;
+    out = make_float4(acc.C0, acc.C1, acc.C2, acc.A);
+    count = acc.n;
 }
 
 template <int INTERP, int U, int G, int SIG, bool PS>
@@ -902,6 +915,150 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
             reinterpret_cast<float4*>(J.out)[pix] = c;
             if (J.out_samples) J.out_samples[pix] = count;
             if (J.out_depth) J.out_depth[pix] = hit ? R.t_first : __builtin_inff();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pooled schedule (one job).  ray_setup_kernel sets up every pixel's ray and
+// appends the rays that keep scan points to a compact list (the others get
+// their empty output at once); raycast_pool_kernel keeps its waves resident
+// and hands the listed rays to groups of G lanes as groups free up, so a
+// wave's lanes stay busy whatever the lengths of its rays.  Each ray is
+// composited row by row exactly as in the tiled schedule with G lanes per ray.
+// ---------------------------------------------------------------------------
+struct RayRec {
+    float pb[3];
+    float d[3];
+    int kb, ke;
+    float t_first;
+    int pixel;
+};
+
+__global__ __launch_bounds__(256) void ray_setup_kernel(const DevJob* __restrict__ jobs, RayRec* __restrict__ rays,
+                                                        int* __restrict__ counters) {
+    const DevJob& J = jobs[0];
+    const int px = (int)(blockIdx.x * 16 + (threadIdx.x & 15));
+    const int py = (int)(blockIdx.y * 16 + (threadIdx.x >> 4));
+    const bool in_image = px < J.width && py < J.height;
+    const bool in_rect = px >= J.cull[0] && px <= J.cull[2] && py >= J.cull[1] && py <= J.cull[3];
+    RaySetup R;
+    const bool hit = in_image && in_rect && setup_ray(J, px, py, R);
+    // one append per wave
+    const unsigned long long m = __ballot(hit);
+    const int lane = (int)(threadIdx.x & 63);
+    int base = 0;
+    if (m) {
+        const int first = __builtin_ctzll(m);
+        if (lane == first) base = atomicAdd(&counters[0], __popcll(m));
+        base = __shfl(base, first);
+    }
+    const size_t pix = (size_t)py * J.width + px;
+    if (hit) {
+        const int slot =
+            base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        RayRec r;
+        for (int a = 0; a < 3; ++a) {
+            r.pb[a] = R.pb[a];
+            r.d[a] = R.d[a];
+        }
+        r.kb = R.kb;
+        r.ke = R.ke;
+        r.t_first = R.t_first;
+        r.pixel = (int)pix;
+        rays[slot] = r;
+    } else if (in_image) {
+        reinterpret_cast<float4*>(J.out)[pix] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (J.out_samples) J.out_samples[pix] = 0;
+        if (J.out_depth) J.out_depth[pix] = __builtin_inff();
+    }
+}
+
+template <int INTERP, int G, int SIGK, bool PS>
+__device__ __forceinline__ bool pool_row(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R, int lane,
+                                         int k0, RayAccum& acc) {
+    if constexpr (SIGK >= 0) {
+        return lanes_row<INTERP, G, SIGK, PS>(J, s_tf, R, lane, k0, acc);
+    } else {
+        switch (J.sig) {
+        case SIG_F32x1: return lanes_row<INTERP, G, SIG_F32x1, PS>(J, s_tf, R, lane, k0, acc);
+        case SIG_PIC3_F32: return lanes_row<INTERP, G, SIG_PIC3_F32, PS>(J, s_tf, R, lane, k0, acc);
+        case SIG_PIC3_F16: return lanes_row<INTERP, G, SIG_PIC3_F16, PS>(J, s_tf, R, lane, k0, acc);
+        case SIG_PIC3_BF16: return lanes_row<INTERP, G, SIG_PIC3_BF16, PS>(J, s_tf, R, lane, k0, acc);
+        case SIG_IL3: return lanes_row<INTERP, G, SIG_IL3, PS>(J, s_tf, R, lane, k0, acc);
+        default: return lanes_row<INTERP, G, SIG_GENERIC, PS>(J, s_tf, R, lane, k0, acc);
+        }
+    }
+}
+
+template <int G, int W, int SIGK>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, 8)))
+void raycast_pool_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ tf_pool,
+                         const RayRec* __restrict__ rays, int* __restrict__ counters) {
+    extern __shared__ float4 s_tf[];
+    const DevJob& J = jobs[0];
+    {
+        const int n = J.n_src * kTfEntries;
+        for (int i = (int)threadIdx.x; i < n; i += kBlockThreads)
+            s_tf[i] = tf_pool[(size_t)J.src[i / kTfEntries].tf_slot * kTfEntries + i % kTfEntries];
+        __syncthreads();
+    }
+    const int n_rays = __builtin_amdgcn_readfirstlane(counters[0]);   // the setup kernel's count
+    const int lane = (int)(threadIdx.x & 63);
+    const int leader = lane & ~(G - 1);
+    constexpr int kChunk = 2 * (64 / G);                                 // rays taken per atomic
+    int q_next = 0, q_end = 0;                                           // the wave's local queue
+    bool exhausted = false, live = false;
+    RaySetup R;
+    int pixel = 0, k0 = 0;
+    RayAccum acc = {0.f, 0.f, 0.f, 0.f, 0};
+    for (;;) {
+        // hand queued rays to the idle groups, in lane order
+        unsigned long long idle = __ballot(!live && lane == leader);
+        while (idle && !exhausted) {
+            if (q_next >= q_end) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&counters[1], kChunk);
+                base = __shfl(base, 0);
+                if (base >= n_rays) {
+                    exhausted = true;
+                    break;
+                }
+                q_next = base;
+                q_end = min(base + kChunk, n_rays);
+            }
+            const int take = min(__popcll(idle), q_end - q_next);
+            const int rank = __popcll(idle & ((1ull << leader) - 1ull));
+            if (!live && rank < take) {
+                const RayRec& rr = rays[q_next + rank];
+                for (int a = 0; a < 3; ++a) {
+                    R.pb[a] = rr.pb[a];
+                    R.d[a] = rr.d[a];
+                }
+                R.kb = rr.kb;
+                R.ke = rr.ke;
+                R.t_first = rr.t_first;
+                pixel = rr.pixel;
+                k0 = R.kb;
+                acc = RayAccum{0.f, 0.f, 0.f, 0.f, 0};
+                live = true;
+            }
+            q_next += take;
+            idle = __ballot(!live && lane == leader);
+        }
+        if (!__ballot(live)) break;
+        if (live) {
+            const bool done = J.interp ? pool_row<1, G, SIGK, (W > 0)>(J, s_tf, R, lane, k0, acc)
+                                       : pool_row<0, G, SIGK, (W > 0)>(J, s_tf, R, lane, k0, acc);
+            k0 += G;
+            if (done) {
+                if (lane == leader) {
+                    reinterpret_cast<float4*>(J.out)[pixel] = make_float4(acc.C0, acc.C1, acc.C2, acc.A);
+                    if (J.out_samples) J.out_samples[pixel] = acc.n;
+                    if (J.out_depth) J.out_depth[pixel] = R.t_first;
+                }
+                live = false;
+            }
         }
     }
 }
@@ -1085,8 +1242,8 @@ __global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
     }
 }
 
-__global__ void reset_counter_kernel(int* c) {
-    if (threadIdx.x == 0) c[0] = 0;
+__global__ void reset_counter_kernel(int* c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
 // Copy a strided field (guard layers included) into a packed buffer of the
@@ -1170,8 +1327,55 @@ int launch_raycast(const LaunchArgs& a, void* stream) {
     return hipGetLastError();
 }
 
+using PoolFn = void (*)(const DevJob*, const float4*, const RayRec*, int*);
+
+template <int SIGK>
+PoolFn pick_pool_specialized(int lanes, int hint) {
+    switch (lanes) {
+    case 16: return hint ? raycast_pool_kernel<16, 4, SIGK> : raycast_pool_kernel<16, 0, SIGK>;
+    case 8: return hint ? raycast_pool_kernel<8, 4, SIGK> : raycast_pool_kernel<8, 0, SIGK>;
+    case 4: return hint ? raycast_pool_kernel<4, 4, SIGK> : raycast_pool_kernel<4, 0, SIGK>;
+    default: return raycast_pool_kernel<2, 0, SIGK>;
+    }
+}
+
+PoolFn pick_pool_kernel(int sig, int lanes, int hint) {
+    switch (sig) {
+    case SIG_F32x1: return pick_pool_specialized<SIG_F32x1>(lanes, hint);
+    case SIG_PIC3_F32: return pick_pool_specialized<SIG_PIC3_F32>(lanes, hint);
+    case SIG_PIC3_F16: return pick_pool_specialized<SIG_PIC3_F16>(lanes, hint);
+    case SIG_PIC3_BF16: return pick_pool_specialized<SIG_PIC3_BF16>(lanes, hint);
+    case SIG_IL3: return pick_pool_specialized<SIG_IL3>(lanes, hint);
+    default: break;
+    }
+    switch (lanes) {
+    case 16: return raycast_pool_kernel<16, 0, -1>;
+    case 8: return raycast_pool_kernel<8, 0, -1>;
+    case 4: return raycast_pool_kernel<4, 0, -1>;
+    default: return raycast_pool_kernel<2, 0, -1>;
+    }
+}
+
+int launch_raycast_pooled(const DevJob* job_dev, int width, int height, const float* tf_pool, int max_src, int sig,
+                          int lanes, int hint, void* rays, int* counters, int n_cu, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counters, 2);
+    const dim3 sgrid((unsigned)((width + 15) / 16), (unsigned)((height + 15) / 16));
+    hipLaunchKernelGGL(ray_setup_kernel, sgrid, dim3(256), 0, st, job_dev, static_cast<RayRec*>(rays), counters);
+    const size_t lds = (size_t)(max_src > 0 ? max_src : 1) * kTfEntries * sizeof(float4);
+    const PoolFn k = pick_pool_kernel(sig, lanes, hint);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlockThreads, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    hipLaunchKernelGGL(k, dim3((unsigned)(n_cu * per_cu)), dim3(kBlockThreads), lds, st, job_dev,
+                       reinterpret_cast<const float4*>(tf_pool), static_cast<const RayRec*>(rays), counters);
+    return hipGetLastError();
+}
+
+size_t ray_record_bytes() { return sizeof(RayRec); }
+
 int launch_reset_counter(int* counter, void* stream) {
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, counter);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, counter, 1);
     return hipGetLastError();
 }
 
