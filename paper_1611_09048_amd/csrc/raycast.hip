@@ -1155,91 +1155,137 @@ __global__ void encode_rgba8_kernel(EncodeArgs a) {
 // interleaved writes are coalesced.  SIG > 0: the sources have that
 // signature's compile-time kinds; SIG = 0: any sources.
 template <int SIG>
+__device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int yi, int zi0, int nz) {
+    constexpr int kZ = 4;                      // z-slices per thread: their loads are in flight together
+    const int ex = a.ext[0], ey = a.ext[1];
+    const int x = xi - a.g, y = yi - a.g;
+    bool need[kZ];
+#pragma unroll
+    for (int j = 0; j < kZ; ++j) {
+        const int z = zi0 + j - a.g;
+        need[j] = j < nz;
+        if (need[j] && a.n_sets > 0) {
+            // a kept scan point reads voxel centres less than one voxel away per axis
+            // (1.5 for the iso-surface gradient), i.e. within 1.5 sqrt(3) < 3 of it
+            // along any unit normal
+            const float c[3] = {a.org[0] + x + 0.5f, a.org[1] + y + 0.5f, a.org[2] + z + 0.5f};
+            bool any = false;
+            for (int k = 0; k < a.n_sets && !any; ++k) {
+                bool inside = true;
+                for (int p = 0; p < a.n_planes[k]; ++p) {
+                    const float* pl = a.planes[k][p];
+                    inside = inside && pl[0] * c[0] + pl[1] * c[1] + pl[2] * c[2] + pl[3] >= -3.f;
+                }
+                any = inside;
+            }
+            need[j] = any;
+        }
+    }
+    // a source without guard layers never has them read: its guard cells hold the border values
+    auto offset = [&](const DevSource& S, int z) {
+        const int qx = S.guard < 1 ? clampi(x, 0, ex - 2 * a.g - 1) : x;
+        const int qy = S.guard < 1 ? clampi(y, 0, ey - 2 * a.g - 1) : y;
+        const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
+        return qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2];
+    };
+    auto store = [&](int j, float o0, float o1, float o2, float o3) {
+        float* d = a.dst + ((int64_t)(zi0 + j) * ey + yi) * ex * a.n + (int64_t)xi * a.n;
+        switch (a.n) {
+        case 4: *reinterpret_cast<float4*>(d) = make_float4(o0, o1, o2, o3); break;
+        case 3: d[0] = o0; d[1] = o1; d[2] = o2; break;
+        case 2: d[0] = o0; d[1] = o1; break;
+        default: d[0] = o0; break;
+        }
+    };
+    if constexpr (SIG == SIG_GENERIC) {
+        // one voxel at a time (any sources)
+#pragma unroll
+        for (int j = 0; j < kZ; ++j) {
+            if (!need[j]) continue;
+            const int z = zi0 + j - a.g;
+            float v[kMaxDerived][1][4];
+#pragma unroll
+            for (int s = 0; s < kMaxDerived; ++s) {
+                if (s < a.n) {
+                    const int off[1] = {offset(a.src[s], z)};
+                    fetch<1>(a.src[s], off, v[s]);
+                }
+            }
+            float o[kMaxDerived] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < kMaxDerived; ++s) {
+                if (s < a.n) {
+                    float r[1];
+                    run_chain<1>(a.src[s], v[s], r);
+                    o[s] = r[0];
+                }
+            }
+            store(j, o[0], o[1], o[2], o[3]);
+        }
+    } else {
+        float out[kZ][kMaxDerived];
+        constexpr int K0 = SigKinds<SIG>::k0, K1 = SigKinds<SIG>::k1, K2 = SigKinds<SIG>::k2;
+        float v0[kZ][4], v1[kZ][4], v2[kZ][4];
+        // every load of the kZ voxels first (a skipped voxel reads its neighbour's address harmlessly)
+#pragma unroll
+        for (int j = 0; j < kZ; ++j) {
+            const int z = zi0 + (need[j] ? j : 0) - a.g;
+            float t[1][4];
+            const int o0[1] = {offset(a.src[0], z)};
+            fetch_kind<K0, 1>(a.src[0], o0, t);
+            for (int c = 0; c < 4; ++c) v0[j][c] = t[0][c];
+            if constexpr (K1 != K_NONE) {
+                const int o1[1] = {offset(a.src[1], z)};
+                fetch_kind<K1, 1>(a.src[1], o1, t);
+                for (int c = 0; c < 4; ++c) v1[j][c] = t[0][c];
+            }
+            if constexpr (K2 != K_NONE) {
+                const int o2[1] = {offset(a.src[2], z)};
+                fetch_kind<K2, 1>(a.src[2], o2, t);
+                for (int c = 0; c < 4; ++c) v2[j][c] = t[0][c];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kZ; ++j) {
+            float t[1][4], r[1];
+            for (int c = 0; c < 4; ++c) t[0][c] = v0[j][c];
+            run_chain<1, KindOf<K0>::dim>(a.src[0], t, r);
+            out[j][0] = r[0];
+            out[j][1] = out[j][2] = out[j][3] = 0.f;
+            if constexpr (K1 != K_NONE) {
+                for (int c = 0; c < 4; ++c) t[0][c] = v1[j][c];
+                run_chain<1, KindOf<K1>::dim>(a.src[1], t, r);
+                out[j][1] = r[0];
+            }
+            if constexpr (K2 != K_NONE) {
+                for (int c = 0; c < 4; ++c) t[0][c] = v2[j][c];
+                run_chain<1, KindOf<K2>::dim>(a.src[2], t, r);
+                out[j][2] = r[0];
+            }
+        }
+        // one contiguous store per voxel
+#pragma unroll
+        for (int j = 0; j < kZ; ++j)
+            if (need[j]) store(j, out[j][0], out[j][1], out[j][2], out[j][3]);
+    }
+}
+
+// Derived volume: every voxel's chain output per source, computed once with
+// the same fetch and chain code as the ray loop (so the values are the ones
+// the loop would compute at that voxel, bit for bit).  Blocks of 256 threads
+// cover consecutive voxels of a z-slice (x fastest: reads and the interleaved
+// writes are coalesced); each thread takes 4 slices with their loads in
+// flight together.  SIG > 0: the sources have that signature's compile-time
+// kinds; SIG = 0: any sources.
+template <int SIG>
 __global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
     const int ex = a.ext[0], ey = a.ext[1];
     const int idx = (int)(blockIdx.x * 256 + threadIdx.x);
     if (idx >= ex * ey) return;
     const int yi = idx / ex;
     const int xi = idx - yi * ex;
-    for (int zi = (int)blockIdx.z; zi < a.ext[2]; zi += (int)gridDim.z) {
-        const int64_t i = (int64_t)zi * ex * ey + idx;
-        const int x = xi - a.g, y = yi - a.g, z = zi - a.g;
-        if (a.n_sets > 0) {
-            // a kept scan point reads voxel centres less than one voxel away per axis
-            // (1.5 for the iso-surface gradient), i.e. within 1.5 sqrt(3) < 3 of it
-            // along any unit normal
-            const float c[3] = {a.org[0] + x + 0.5f, a.org[1] + y + 0.5f, a.org[2] + z + 0.5f};
-            bool needed = false;
-            for (int k = 0; k < a.n_sets && !needed; ++k) {
-                bool inside = true;
-                for (int p = 0; p < a.n_planes[k]; ++p) {
-                    const float* pl = a.planes[k][p];
-                    inside = inside && pl[0] * c[0] + pl[1] * c[1] + pl[2] * c[2] + pl[3] >= -3.f;
-                }
-                needed = inside;
-            }
-            if (!needed) continue;
-        }
-        // a source without guard layers never has them read: its guard cells hold the border values
-        auto offset = [&](const DevSource& S) {
-            const int qx = S.guard < 1 ? clampi(x, 0, ex - 2 * a.g - 1) : x;
-            const int qy = S.guard < 1 ? clampi(y, 0, ey - 2 * a.g - 1) : y;
-            const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
-            return qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2];
-        };
-        float out[kMaxDerived] = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (SIG == SIG_GENERIC) {
-            // every source's loads first, then the chains
-            float v[kMaxDerived][1][4];
-#pragma unroll
-            for (int s = 0; s < kMaxDerived; ++s) {
-                if (s < a.n) {
-                    const int off[1] = {offset(a.src[s])};
-                    fetch<1>(a.src[s], off, v[s]);
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < kMaxDerived; ++s) {
-                if (s < a.n) {
-                    float r[1];
-                    run_chain<1>(a.src[s], v[s], r);
-                    out[s] = r[0];
-                }
-            }
-        } else {
-            constexpr int K0 = SigKinds<SIG>::k0, K1 = SigKinds<SIG>::k1, K2 = SigKinds<SIG>::k2;
-            float v0[1][4], v1[1][4], v2[1][4];
-            const int o0[1] = {offset(a.src[0])};
-            fetch_kind<K0, 1>(a.src[0], o0, v0);
-            if constexpr (K1 != K_NONE) {
-                const int o1[1] = {offset(a.src[1])};
-                fetch_kind<K1, 1>(a.src[1], o1, v1);
-            }
-            if constexpr (K2 != K_NONE) {
-                const int o2[1] = {offset(a.src[2])};
-                fetch_kind<K2, 1>(a.src[2], o2, v2);
-            }
-            float r[1];
-            run_chain<1, KindOf<K0>::dim>(a.src[0], v0, r);
-            out[0] = r[0];
-            if constexpr (K1 != K_NONE) {
-                run_chain<1, KindOf<K1>::dim>(a.src[1], v1, r);
-                out[1] = r[0];
-            }
-            if constexpr (K2 != K_NONE) {
-                run_chain<1, KindOf<K2>::dim>(a.src[2], v2, r);
-                out[2] = r[0];
-            }
-        }
-        // one contiguous store per voxel
-        float* d = a.dst + i * a.n;
-        switch (a.n) {
-        case 4: *reinterpret_cast<float4*>(d) = make_float4(out[0], out[1], out[2], out[3]); break;
-        case 3: d[0] = out[0]; d[1] = out[1]; d[2] = out[2]; break;
-        case 2: d[0] = out[0]; d[1] = out[1]; break;
-        default: d[0] = out[0]; break;
-        }
-    }
+    for (int zi0 = 4 * (int)blockIdx.z; zi0 < a.ext[2]; zi0 += 4 * (int)gridDim.z)
+        derive_voxels<SIG>(a, xi, yi, zi0, min(4, a.ext[2] - zi0));
 }
 
 __global__ void reset_counter_kernel(int* c, int n) {
@@ -1433,7 +1479,7 @@ int launch_derive(const DeriveArgs& a, int sig, void* stream) {
     if (a.ext[0] <= 0 || a.ext[1] <= 0 || a.ext[2] <= 0) return hipSuccess;
     const int64_t slice = (int64_t)a.ext[0] * a.ext[1];
     if (slice > (1LL << 30)) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((slice + 255) / 256), 1, (unsigned)std::min(a.ext[2], 65535));
+    const dim3 grid((unsigned)((slice + 255) / 256), 1, (unsigned)std::min((a.ext[2] + 3) / 4, 65535));
     void (*k)(DeriveArgs) = derive_kernel<SIG_GENERIC>;
     switch (sig) {
     case SIG_F32x1: k = derive_kernel<SIG_F32x1>; break;
