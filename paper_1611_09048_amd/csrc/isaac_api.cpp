@@ -231,7 +231,8 @@ struct RingSlot {
     // graph cache
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    int g_jobs = -1, g_tiles = -1, g_grid = -1, g_src = -1, g_unroll = -1, g_lanes = -1, g_hint = -1, g_sig = -2;
+    int g_jobs = -1, g_tiles = -1, g_grid = -1, g_src = -1, g_unroll = -1, g_lanes = -1, g_hint = -1, g_sig = -3;
+    unsigned g_fill = 0;
 };
 
 struct Pending {
@@ -495,14 +496,17 @@ int32_t signature_of(const DevJob& dj) {
 }
 
 // Tile decomposition of a job for a launch running `lanes` lanes per ray.
+// Tiles cover only the job's screen rectangle (cull); the pixels outside it
+// are cleared by a fill kernel.
 void set_tiles(DevJob& dj, int lanes, int unroll) {
     dj.lanes = lanes;
     dj.unroll = lanes > 1 ? 1 : unroll;
     const int rays = 64 / lanes;
     if (dj.wave_w > rays) dj.wave_w = rays;
     const int tw = dj.wave_w * dj.waves_x, th = (rays / dj.wave_w) * (4 / dj.waves_x);
-    dj.tiles_x = (dj.width + tw - 1) / tw;
-    dj.tiles_y = (dj.height + th - 1) / th;
+    const int rw = std::max(0, dj.cull[2] - dj.cull[0] + 1), rh = std::max(0, dj.cull[3] - dj.cull[1] + 1);
+    dj.tiles_x = (rw + tw - 1) / tw;
+    dj.tiles_y = rw > 0 ? (rh + th - 1) / th : 0;
 }
 
 // A pixel rectangle containing every pixel whose ray can meet the box (the
@@ -818,6 +822,11 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     if (la.sig == SIG_GENERIC) la.sig = -1;
     la.mode = djs[0].mode;
     if (la.mode == ISAAC_ISO) la.sig = -2;
+    {
+        size_t maxpix = 1;
+        for (const DevJob& dj : djs) maxpix = std::max(maxpix, (size_t)dj.width * dj.height);
+        la.fill_blocks = (unsigned)std::min<size_t>((maxpix + 1023) / 1024, 1024);
+    }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (flags & ISAAC_TIMING) {
         t0 = get_event(ctx);
@@ -827,7 +836,8 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     const bool use_graph = n > 1 && !(flags & ISAAC_NO_GRAPH);
     if (use_graph) {
         if (!r->exec || r->g_jobs != n || r->g_tiles != tiles || r->g_grid != la.grid || r->g_src != la.max_src ||
-            r->g_unroll != la.unroll || r->g_lanes != la.lanes || r->g_hint != la.waves_hint || r->g_sig != la.sig) {
+            r->g_unroll != la.unroll || r->g_lanes != la.lanes || r->g_hint != la.waves_hint || r->g_sig != la.sig ||
+            r->g_fill != la.fill_blocks) {
             if (r->exec) hipGraphExecDestroy(r->exec);
             if (r->graph) hipGraphDestroy(r->graph);
             r->exec = nullptr;
@@ -853,6 +863,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
             r->g_lanes = la.lanes;
             r->g_hint = la.waves_hint;
             r->g_sig = la.sig;
+            r->g_fill = la.fill_blocks;
         }
         if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
         HIP_TRY(ctx, hipGraphLaunch(r->exec, stream));

@@ -117,6 +117,7 @@ struct LaunchArgs {
     int waves_hint;            // 1: the variant compiled for at least 4 waves per SIMD
     int sig;                   // the jobs' common Signature, or -1 when they differ
     int mode;                  // 1: iso-surface jobs (all jobs of a launch share the mode)
+    unsigned fill_blocks;      // blocks per job of the fill of pixels outside the screen rectangles
 };
 
 int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t

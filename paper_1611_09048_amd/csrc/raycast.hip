@@ -845,9 +845,9 @@ __device__ __forceinline__ bool pixel_of(const DevJob& J, int t, int lane, int w
     const int ww = J.wave_w, wh = (64 / G) / ww;
     const int gx = J.waves_x, gy = 4 / gx;
     const int tx = t % J.tiles_x, ty = t / J.tiles_x;
-    px = tx * (ww * gx) + (wave % gx) * ww + ray % ww;
-    py = ty * (wh * gy) + (wave / gx) * wh + ray / ww;
-    return px < J.width && py < J.height;
+    px = J.cull[0] + tx * (ww * gx) + (wave % gx) * ww + ray % ww;
+    py = J.cull[1] + ty * (wh * gy) + (wave / gx) * wh + ray / ww;
+    return px <= J.cull[2] && py <= J.cull[3];
 }
 
 // Waves-per-SIMD hint: W = 0 leaves register allocation to the compiler and
@@ -879,12 +879,11 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         tile = __builtin_amdgcn_readfirstlane(tile);
         const int job = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, tile));
         const DevJob& J = jobs[job];
+        // tiles cover the box's screen rectangle only (the fill kernel clears the rest)
         int px = 0, py = 0;
         const bool in_image = pixel_of<G>(J, tile - J.tile_begin, lane, wave, px, py);
-        // pixels outside the box's screen rectangle skip the FP64 setup
-        const bool in_rect = px >= J.cull[0] && px <= J.cull[2] && py >= J.cull[1] && py <= J.cull[3];
         RaySetup R;
-        const bool hit = in_image && in_rect && setup_ray(J, px, py, R);
+        const bool hit = in_image && setup_ray(J, px, py, R);
         // tiles no ray of which meets the box skip the transfer tables; the
         // barrier also ends every read of the previous tile's tables
         if (__syncthreads_or(hit) && job != cur_job) {
@@ -1288,6 +1287,20 @@ __global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
         derive_voxels<SIG>(a, xi, yi, zi0, min(4, a.ext[2] - zi0));
 }
 
+// Clear the output of every pixel outside its job's screen rectangle (no ray
+// there can meet the box): transparent black, 0 samples, depth +inf.
+__global__ void fill_outside_kernel(const DevJob* __restrict__ jobs) {
+    const DevJob& J = jobs[blockIdx.y];
+    const int n = J.width * J.height;
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x)) {
+        const int py = i / J.width, px = i - py * J.width;
+        if (px >= J.cull[0] && px <= J.cull[2] && py >= J.cull[1] && py <= J.cull[3]) continue;
+        reinterpret_cast<float4*>(J.out)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (J.out_samples) J.out_samples[i] = 0;
+        if (J.out_depth) J.out_depth[i] = __builtin_inff();
+    }
+}
+
 __global__ void reset_counter_kernel(int* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
@@ -1363,10 +1376,13 @@ KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
 }
 
 int launch_raycast(const LaunchArgs& a, void* stream) {
+    // pixels outside the jobs' screen rectangles first
+    hipLaunchKernelGGL(fill_outside_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0, (hipStream_t)stream,
+                       a.jobs);
     // dynamic LDS: one 256-entry RGBA32F table per active source of the widest job
     const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfEntries * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
-    if (blocks == 0) return hipSuccess;
+    if (blocks == 0) return hipGetLastError();
     const KernelFn kernel = pick_kernel(a.mode, a.sig, a.unroll, a.lanes, a.waves_hint);
     hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlockThreads), lds, (hipStream_t)stream, a.jobs,
                        reinterpret_cast<const float4*>(a.tf_pool), a.cursor, a.n_jobs, a.total_tiles, a.persistent);
