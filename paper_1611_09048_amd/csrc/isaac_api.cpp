@@ -233,6 +233,7 @@ struct RingSlot {
     hipGraph_t graph = nullptr;
     int g_jobs = -1, g_tiles = -1, g_grid = -1, g_src = -1, g_unroll = -1, g_lanes = -1, g_hint = -1, g_sig = -3;
     unsigned g_fill = 0;
+    int g_dense = -1;
 };
 
 struct Pending {
@@ -827,6 +828,26 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
         for (const DevJob& dj : djs) maxpix = std::max(maxpix, (size_t)dj.width * dj.height);
         la.fill_blocks = (unsigned)std::min<size_t>((maxpix + 1023) / 1024, 1024);
     }
+    // render calls on the context stream set up the rays in a pass of their own
+    // (one lane per ray) into the context's ray buffer
+    la.dense_setup = 0;
+    if (allow_pool) {
+        size_t total = 0;
+        for (int i = 0; i < n; ++i) {
+            const DevJob& dj = r->host[i];
+            total += (size_t)std::max(0, dj.cull[2] - dj.cull[0] + 1) * std::max(0, dj.cull[3] - dj.cull[1] + 1);
+        }
+        if (total > 0 && total * ray_record_bytes() < ((size_t)1 << 31) &&
+            ensure_pool(ctx, total * ray_record_bytes(), stream)) {
+            size_t off = 0;
+            for (int i = 0; i < n; ++i) {
+                DevJob& dj = r->host[i];
+                dj.rays = static_cast<char*>(ctx->pool_rays) + off * ray_record_bytes();
+                off += (size_t)std::max(0, dj.cull[2] - dj.cull[0] + 1) * std::max(0, dj.cull[3] - dj.cull[1] + 1);
+            }
+            la.dense_setup = 1;
+        }
+    }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (flags & ISAAC_TIMING) {
         t0 = get_event(ctx);
@@ -837,7 +858,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     if (use_graph) {
         if (!r->exec || r->g_jobs != n || r->g_tiles != tiles || r->g_grid != la.grid || r->g_src != la.max_src ||
             r->g_unroll != la.unroll || r->g_lanes != la.lanes || r->g_hint != la.waves_hint || r->g_sig != la.sig ||
-            r->g_fill != la.fill_blocks) {
+            r->g_fill != la.fill_blocks || r->g_dense != la.dense_setup) {
             if (r->exec) hipGraphExecDestroy(r->exec);
             if (r->graph) hipGraphDestroy(r->graph);
             r->exec = nullptr;
@@ -864,6 +885,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
             r->g_hint = la.waves_hint;
             r->g_sig = la.sig;
             r->g_fill = la.fill_blocks;
+            r->g_dense = la.dense_setup;
         }
         if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
         HIP_TRY(ctx, hipGraphLaunch(r->exec, stream));

@@ -98,6 +98,7 @@ struct DevJob {
     float* out;            // device RGBA32F image
     int32_t* out_samples;  // device per-pixel sample counts or null
     float* out_depth;      // device per-pixel ray parameter of the first scan point (+inf: none) or null
+    void* rays;            // device ray records over the screen rectangle (set up by a separate pass) or null
     int32_t src_index[kMaxSources];  // volume source index of each active source (host bookkeeping)
     DevSource src[kMaxSources];
 };
@@ -118,6 +119,7 @@ struct LaunchArgs {
     int sig;                   // the jobs' common Signature, or -1 when they differ
     int mode;                  // 1: iso-surface jobs (all jobs of a launch share the mode)
     unsigned fill_blocks;      // blocks per job of the fill of pixels outside the screen rectangles
+    int dense_setup;           // 1: set up every ray of the jobs' rectangles into DevJob::rays first
 };
 
 int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t

@@ -247,6 +247,15 @@ struct RaySetup {
     float t_first;         // ray parameter of scan point kb
 };
 
+// A set-up ray as stored by the setup passes (40 bytes).
+struct RayRec {
+    float pb[3];
+    float d[3];
+    int kb, ke;
+    float t_first;
+    int pixel;
+};
+
 // Scan point k in the volume's own index space: the global position minus the
 // brick origin (an exact FP32 subtraction of an integer below the position).
 __device__ __forceinline__ void point_at(const DevJob& J, const RaySetup& R, float tk, float (&p)[3]) {
@@ -883,7 +892,27 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         int px = 0, py = 0;
         const bool in_image = pixel_of<G>(J, tile - J.tile_begin, lane, wave, px, py);
         RaySetup R;
-        const bool hit = in_image && setup_ray(J, px, py, R);
+        bool hit;
+        if (J.rays) {
+            // set up by ray_setup_dense_kernel, one lane per ray
+            hit = false;
+            if (in_image) {
+                const int rw = J.cull[2] - J.cull[0] + 1;
+                const RayRec& rr = static_cast<const RayRec*>(J.rays)[(py - J.cull[1]) * rw + (px - J.cull[0])];
+                R.kb = rr.kb;
+                R.ke = rr.ke;
+                hit = R.kb < R.ke;
+                if (hit) {
+                    for (int a = 0; a < 3; ++a) {
+                        R.pb[a] = rr.pb[a];
+                        R.d[a] = rr.d[a];
+                    }
+                    R.t_first = rr.t_first;
+                }
+            }
+        } else {
+            hit = in_image && setup_ray(J, px, py, R);
+        }
         // tiles no ray of which meets the box skip the transfer tables; the
         // barrier also ends every read of the previous tile's tables
         if (__syncthreads_or(hit) && job != cur_job) {
@@ -926,14 +955,6 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
 // wave's lanes stay busy whatever the lengths of its rays.  Each ray is
 // composited row by row exactly as in the tiled schedule with G lanes per ray.
 // ---------------------------------------------------------------------------
-struct RayRec {
-    float pb[3];
-    float d[3];
-    int kb, ke;
-    float t_first;
-    int pixel;
-};
-
 __global__ __launch_bounds__(256) void ray_setup_kernel(const DevJob* __restrict__ jobs, RayRec* __restrict__ rays,
                                                         int* __restrict__ counters) {
     const DevJob& J = jobs[0];
@@ -1180,6 +1201,10 @@ __device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int y
             need[j] = any;
         }
     }
+    bool any_needed = false;
+#pragma unroll
+    for (int j = 0; j < kZ; ++j) any_needed = any_needed || need[j];
+    if (!any_needed) return;
     // a source without guard layers never has them read: its guard cells hold the border values
     auto offset = [&](const DevSource& S, int z) {
         const int qx = S.guard < 1 ? clampi(x, 0, ex - 2 * a.g - 1) : x;
@@ -1287,6 +1312,38 @@ __global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
         derive_voxels<SIG>(a, xi, yi, zi0, min(4, a.ext[2] - zi0));
 }
 
+// Ray setup of every pixel of each job's screen rectangle, one lane per ray,
+// into the job's ray records (kb = ke = 0: no scan point); the ray-casting
+// kernel then reads a record instead of repeating the FP64 setup on every
+// lane of a ray's group.
+__global__ __launch_bounds__(256) void ray_setup_dense_kernel(const DevJob* __restrict__ jobs) {
+    const DevJob& J = jobs[blockIdx.y];
+    const int rw = J.cull[2] - J.cull[0] + 1, rh = J.cull[3] - J.cull[1] + 1;
+    if (rw <= 0 || rh <= 0) return;
+    RayRec* rays = static_cast<RayRec*>(J.rays);
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < rw * rh; i += (int)(gridDim.x * blockDim.x)) {
+        const int ry = i / rw, rx = i - ry * rw;
+        const int px = J.cull[0] + rx, py = J.cull[1] + ry;
+        RaySetup R;
+        RayRec r;
+        if (setup_ray(J, px, py, R)) {
+            for (int a = 0; a < 3; ++a) {
+                r.pb[a] = R.pb[a];
+                r.d[a] = R.d[a];
+            }
+            r.kb = R.kb;
+            r.ke = R.ke;
+            r.t_first = R.t_first;
+        } else {
+            for (int a = 0; a < 3; ++a) r.pb[a] = r.d[a] = 0.f;
+            r.kb = r.ke = 0;
+            r.t_first = 0.f;
+        }
+        r.pixel = py * J.width + px;
+        rays[i] = r;
+    }
+}
+
 // Clear the output of every pixel outside its job's screen rectangle (no ray
 // there can meet the box): transparent black, 0 samples, depth +inf.
 __global__ void fill_outside_kernel(const DevJob* __restrict__ jobs) {
@@ -1379,6 +1436,9 @@ int launch_raycast(const LaunchArgs& a, void* stream) {
     // pixels outside the jobs' screen rectangles first
     hipLaunchKernelGGL(fill_outside_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0, (hipStream_t)stream,
                        a.jobs);
+    if (a.dense_setup)
+        hipLaunchKernelGGL(ray_setup_dense_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0,
+                           (hipStream_t)stream, a.jobs);
     // dynamic LDS: one 256-entry RGBA32F table per active source of the widest job
     const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfEntries * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
