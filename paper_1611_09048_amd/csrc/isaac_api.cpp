@@ -379,7 +379,14 @@ isaac_status new_tf_slot(isaac_context* ctx, const float* table, int32_t* handle
         }
     if (slot < 0)
         return set_err(ctx, ISAAC_ERR_OUT_OF_MEMORY, "all %d transfer tables are live; release some", ctx->tf_capacity);
-    HIP_TRY(ctx, hipMemcpy(ctx->tf_pool + (size_t)slot * kTfEntries * 4, table, kTfEntries * 4 * sizeof(float),
+    // device layout: per entry the value and the difference to the next entry (FP32, as the lookup uses it)
+    float rows[kTfRows * 4];
+    for (int j = 0; j < kTfEntries; ++j)
+        for (int c = 0; c < 4; ++c) {
+            rows[8 * j + c] = table[4 * j + c];
+            rows[8 * j + 4 + c] = j + 1 < kTfEntries ? table[4 * (j + 1) + c] - table[4 * j + c] : 0.0f;
+        }
+    HIP_TRY(ctx, hipMemcpy(ctx->tf_pool + (size_t)slot * kTfRows * 4, rows, kTfRows * 4 * sizeof(float),
                            hipMemcpyHostToDevice));
     ctx->tf_slots[slot] = TfSlot();
     ctx->tf_slots[slot].live = true;
@@ -475,7 +482,7 @@ int32_t signature_of(const DevJob& dj) {
         for (int s = 0; s < 3; ++s)
             il = il && d[s].f_dim == 1 && d[s].dtype == DT_F32 && d[s].n_ops == 0 && d[s].base[0] == d[0].base[0] &&
                  d[s].num_records[0] == d[0].num_records[0] && d[s].comp_off[0] == d[0].comp_off[0] + 4 * s &&
-                 d[s].guard == d[0].guard && d[s].stride[0] == 12 && d[s].stride[1] == d[0].stride[1] &&
+                 d[s].guard >= 1 && d[s].stride[0] == 12 && d[s].stride[1] == d[0].stride[1] &&
                  d[s].stride[2] == d[0].stride[2] && d[s].stride[1] < (1 << 23) && d[s].stride[2] < (1 << 23);
         if (il) return SIG_IL3;
     }
@@ -485,6 +492,7 @@ int32_t signature_of(const DevJob& dj) {
         bool small = true;
         for (int a = 0; a < 3; ++a) small = small && std::abs((int64_t)d.stride[a]) < (1 << 23);
         if (!d.packed || !small || (d.f_dim != 1 && d.f_dim != 3)) return SIG_GENERIC;
+        if (dj.n_src == 3 && d.guard < 1) return SIG_GENERIC;   // the three-source loops assume guard layers
         kinds[s] = d.dtype * 2 + (d.f_dim == 3 ? 1 : 0);   // dtype-major: F32x1=0, F32x3=1, F16x1=2, ...
     }
     if (dj.n_src == 1 && kinds[0] == 0) return SIG_F32x1;
@@ -1219,12 +1227,12 @@ isaac_status isaac_init(const isaac_init_desc* desc, isaac_context** out) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
         if (e != hipSuccess) return fail("staging ring", e);
     }
-    e = hipMalloc((void**)&ctx->tf_pool, (size_t)kTfSlots * kTfEntries * 4 * sizeof(float));
+    e = hipMalloc((void**)&ctx->tf_pool, (size_t)kTfSlots * kTfRows * 4 * sizeof(float));
     if (e != hipSuccess) return fail("transfer table pool", e);
     ctx->tf_capacity = kTfSlots;
     ctx->tf_slots.resize(kTfSlots);
     // slot 0: the all-zero table of sources without a transfer function
-    e = hipMemset(ctx->tf_pool, 0, kTfEntries * 4 * sizeof(float));
+    e = hipMemset(ctx->tf_pool, 0, kTfRows * 4 * sizeof(float));
     if (e != hipSuccess) return fail("hipMemset", e);
     ctx->tf_slots[0].live = true;
     e = hipDeviceSynchronize();

@@ -11,6 +11,9 @@ constexpr int kMaxSources = 8;
 constexpr int kMaxOps = 8;
 constexpr int kMaxClip = 8;
 constexpr int kTfEntries = 256;
+// A table as stored on the device: per entry j two RGBA32F rows, T[j] and
+// T[j+1] - T[j] (the last difference is 0), so a lookup is one FMA per channel.
+constexpr int kTfRows = 2 * kTfEntries;
 constexpr int kMaxBatch = 256;
 constexpr int kBlockThreads = 256;     // 4 waves of 64
 

@@ -229,10 +229,9 @@ __device__ __forceinline__ float4 classify(const float4* __restrict__ table, flo
     float u = 255.f * t;
     int j = min((int)u, 254);
     float f = u - (float)j;
-    float4 a = table[j];
-    float4 b = table[j + 1];
-    return make_float4(fmaf(f, b.x - a.x, a.x), fmaf(f, b.y - a.y, a.y), fmaf(f, b.z - a.z, a.z),
-                       fmaf(f, b.w - a.w, a.w));
+    const float4 a = table[2 * j];          // T[j]
+    const float4 d = table[2 * j + 1];      // T[j+1] - T[j]
+    return make_float4(fmaf(f, d.x, a.x), fmaf(f, d.y, a.y), fmaf(f, d.z, a.z), fmaf(f, d.w, a.w));
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
@@ -406,7 +405,7 @@ template <> struct KindOf<K_BF16x3> { static constexpr int dim = 3, dtype = DT_B
 // Voxel offsets of one source: nearest cell, or the 8 trilinear corners with
 // the border clamp of guard-less sources.  24-bit multiplies (the host admits
 // a signature only when every stride is below 2^23 bytes).
-template <int INTERP>
+template <int INTERP, bool CLAMP = true>
 __device__ __forceinline__ void corner_offsets(const DevSource& S, const int dims[3], const int (&i0)[3],
                                                int (&off)[INTERP ? 8 : 1]) {
     if (INTERP == 0) {
@@ -418,7 +417,7 @@ __device__ __forceinline__ void corner_offsets(const DevSource& S, const int dim
     for (int a = 0; a < 3; ++a) {
         a0[a] = i0[a];
         a1[a] = i0[a] + 1;
-        if (S.guard < 1) {
+        if (CLAMP && S.guard < 1) {
             a0[a] = clampi(a0[a], 0, dims[a] - 1);
             a1[a] = clampi(a1[a], 0, dims[a] - 1);
         }
@@ -496,7 +495,7 @@ __device__ __forceinline__ void point_generic(const DevJob& J, const float4* __r
     for (int s = 0; s < J.n_src; ++s) {
         const DevSource& src = J.src[s];
         const float x = sample_source<INTERP>(src, dims, p);
-        const float4 c = classify(s_tf + s * kTfEntries, x);
+        const float4 c = classify(s_tf + s * kTfRows, x);
         const float wa = src.weight * c.w;
         S += wa;
         E[0] = fmaf(wa, c.x, E[0]);
@@ -527,6 +526,8 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
         constexpr int KS[3] = {K0, K1, K2};
         constexpr int NV = INTERP ? 8 : 1;
         constexpr int NS = (K0 != K_NONE) + (K1 != K_NONE) + (K2 != K_NONE);
+        // the host admits the three-source signatures only with guard layers: no border clamp
+        constexpr bool CL = SIG == SIG_F32x1;
         const float step = (float)J.step;
         const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
         int i0[U][3];
@@ -553,7 +554,7 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
             E[u][0] = E[u][1] = E[u][2] = 0.f;
         }
         auto accumulate = [&](int u, int s, float x) {
-            const float4 cl = classify(s_tf + s * kTfEntries, x);
+            const float4 cl = classify(s_tf + s * kTfRows, x);
             const float wa = J.src[s].weight * cl.w;
             S[u] += wa;
             E[u][0] = fmaf(wa, cl.x, E[u][0]);
@@ -566,7 +567,7 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
             for (int u = 0; u < U; ++u) {
                 int off[NV];
                 float v[NV][4];
-                corner_offsets<INTERP>(J.src[0], dims, i0[u], off);
+                corner_offsets<INTERP, CL>(J.src[0], dims, i0[u], off);
                 fetch_kind<K_F32x3, NV>(J.src[0], off, v);
 #pragma unroll
                 for (int s = 0; s < 3; ++s) {
@@ -583,7 +584,7 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
                 for (int u = 0; u < U; ++u) {
                     int off[NV];
                     float v[NV][4], c[NV];
-                    corner_offsets<INTERP>(J.src[s], dims, i0[u], off);
+                    corner_offsets<INTERP, CL>(J.src[s], dims, i0[u], off);
                     if (s == 0) fetch_kind<KS[0], NV>(J.src[0], off, v);
                     else if (s == 1) fetch_kind<KS[1], NV>(J.src[1], off, v);
                     else fetch_kind<KS[2], NV>(J.src[2], off, v);
@@ -600,15 +601,15 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
             for (int u = 0; u < U; ++u) {
                 int off[NV];
                 if (NS > 0) {
-                    corner_offsets<INTERP>(J.src[0], dims, i0[u], off);
+                    corner_offsets<INTERP, CL>(J.src[0], dims, i0[u], off);
                     fetch_kind<K0, NV>(J.src[0], off, vals[u][0]);
                 }
                 if (NS > 1) {
-                    corner_offsets<INTERP>(J.src[1], dims, i0[u], off);
+                    corner_offsets<INTERP, CL>(J.src[1], dims, i0[u], off);
                     fetch_kind<K1, NV>(J.src[1], off, vals[u][1]);
                 }
                 if (NS > 2) {
-                    corner_offsets<INTERP>(J.src[2], dims, i0[u], off);
+                    corner_offsets<INTERP, CL>(J.src[2], dims, i0[u], off);
                     fetch_kind<K2, NV>(J.src[2], off, vals[u][2]);
                 }
             }
@@ -831,7 +832,7 @@ __device__ __forceinline__ void march_iso(const DevJob& J, const float4* __restr
         const float gl = sqrtf(fmaf(g[0], g[0], fmaf(g[1], g[1], g[2] * g[2])));
         const float cosine = gl > 0.f ? fabsf(fmaf(g[0], R.d[0], fmaf(g[1], R.d[1], g[2] * R.d[2]))) / gl : 1.f;
         const float light = fmaf(0.7f, fminf(cosine, 1.f), 0.3f);
-        const float4 c = classify(s_tf + s * kTfEntries, S.iso);
+        const float4 c = classify(s_tf + s * kTfRows, S.iso);
         out = make_float4(c.x * light, c.y * light, c.z * light, 1.f);
     }
 }
@@ -916,10 +917,10 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         // tiles no ray of which meets the box skip the transfer tables; the
         // barrier also ends every read of the previous tile's tables
         if (__syncthreads_or(hit) && job != cur_job) {
-            const int n = J.n_src * kTfEntries;
+            const int n = J.n_src * kTfRows;
             for (int i = threadIdx.x; i < n; i += kBlockThreads) {
-                const int s = i / kTfEntries, e = i % kTfEntries;
-                s_tf[i] = tf_pool[(size_t)J.src[s].tf_slot * kTfEntries + e];
+                const int s = i / kTfRows, e = i % kTfRows;
+                s_tf[i] = tf_pool[(size_t)J.src[s].tf_slot * kTfRows + e];
             }
             __syncthreads();
             cur_job = job;
@@ -1018,9 +1019,9 @@ void raycast_pool_kernel(const DevJob* __restrict__ jobs, const float4* __restri
     extern __shared__ float4 s_tf[];
     const DevJob& J = jobs[0];
     {
-        const int n = J.n_src * kTfEntries;
+        const int n = J.n_src * kTfRows;
         for (int i = (int)threadIdx.x; i < n; i += kBlockThreads)
-            s_tf[i] = tf_pool[(size_t)J.src[i / kTfEntries].tf_slot * kTfEntries + i % kTfEntries];
+            s_tf[i] = tf_pool[(size_t)J.src[i / kTfRows].tf_slot * kTfRows + i % kTfRows];
         __syncthreads();
     }
     const int n_rays = __builtin_amdgcn_readfirstlane(counters[0]);   // the setup kernel's count
@@ -1440,7 +1441,7 @@ int launch_raycast(const LaunchArgs& a, void* stream) {
         hipLaunchKernelGGL(ray_setup_dense_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0,
                            (hipStream_t)stream, a.jobs);
     // dynamic LDS: one 256-entry RGBA32F table per active source of the widest job
-    const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfEntries * sizeof(float4);
+    const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfRows * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
     if (blocks == 0) return hipGetLastError();
     const KernelFn kernel = pick_kernel(a.mode, a.sig, a.unroll, a.lanes, a.waves_hint);
@@ -1484,7 +1485,7 @@ int launch_raycast_pooled(const DevJob* job_dev, int width, int height, const fl
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counters, 2);
     const dim3 sgrid((unsigned)((width + 15) / 16), (unsigned)((height + 15) / 16));
     hipLaunchKernelGGL(ray_setup_kernel, sgrid, dim3(256), 0, st, job_dev, static_cast<RayRec*>(rays), counters);
-    const size_t lds = (size_t)(max_src > 0 ? max_src : 1) * kTfEntries * sizeof(float4);
+    const size_t lds = (size_t)(max_src > 0 ? max_src : 1) * kTfRows * sizeof(float4);
     const PoolFn k = pick_pool_kernel(sig, lanes, hint);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlockThreads, lds) != hipSuccess || per_cu < 1)
@@ -1570,7 +1571,7 @@ int launch_derive(const DeriveArgs& a, int sig, void* stream) {
 
 int raycast_occupancy(int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, raycast_kernel<1, 1, 0, -1>, kBlockThreads,
-                                                       3 * kTfEntries * sizeof(float4));
+                                                       3 * kTfRows * sizeof(float4));
 }
 
 }  // namespace isaac
