@@ -667,31 +667,21 @@ __device__ __forceinline__ float lane_up(float x) {
                                                                  true));
 }
 
-// G lanes per ray: lane g evaluates scan points kb + g, kb + g + G, ...; each
-// row of G points is composited in order with an inclusive scan of the
-// associative front-to-back operator (C, A) o (C', A') = (C + (1-A) C',
-// A + (1-A) A') across the group, then appended to the ray's running state.
-// The first point whose cumulative opacity reaches ert ends the ray, exactly
-// where the one-lane loop would stop.
 // Running front-to-back state of one ray composited by a group of G lanes.
 struct RayAccum {
     float C0, C1, C2, A;
     int n;
 };
 
-// One row of the lanes-per-ray schedule: scan points k0 .. k0+G-1 (those
-// below R.ke), composited into acc.  Returns true when the ray is finished
-// (termination, or no scan point left).
-template <int INTERP, int G, int SIG, bool PS>
-__device__ __forceinline__ bool lanes_row(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
-                                          int lane, int k0, RayAccum& acc) {
+// Composite one row of G scan points (k0 .. k0+G-1; lane g holds point
+// k0 + g, `valid` when below R.ke) into acc: an inclusive scan of the
+// front-to-back operator across the group, then termination at the first
+// point whose cumulative opacity reaches ert.  Returns true when the ray is
+// finished (termination, or no scan point left).
+template <int G>
+__device__ __forceinline__ bool row_composite(const DevJob& J, const RaySetup& R, int lane, int k0, bool valid,
+                                              float c0, float c1, float c2, float a, RayAccum& acc) {
     const int g = lane & (G - 1);
-    const int k = k0 + g;
-    const bool valid = k < R.ke;
-    float E[1][3], S[1];
-    points<INTERP, 1, SIG, PS>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
-    float c0 = valid ? E[0][0] : 0.f, c1 = valid ? E[0][1] : 0.f, c2 = valid ? E[0][2] : 0.f;
-    float a = valid ? S[0] : 0.f;
     // inclusive scan inside each row of 16 lanes ...
 #pragma unroll
     for (int d = 1; d < (G < 16 ? G : 16); d <<= 1) {
@@ -743,6 +733,103 @@ __device__ __forceinline__ bool lanes_row(const DevJob& J, const float4* __restr
     return stop || k0 + G >= R.ke;
 }
 
+// One row of the lanes-per-ray schedule: scan points k0 .. k0+G-1 (those
+// below R.ke), composited into acc.  Returns true when the ray is finished.
+template <int INTERP, int G, int SIG, bool PS>
+__device__ __forceinline__ bool lanes_row(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                          int lane, int k0, RayAccum& acc) {
+    const int g = lane & (G - 1);
+    const int k = k0 + g;
+    const bool valid = k < R.ke;
+    float E[1][3], S[1];
+    points<INTERP, 1, SIG, PS>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
+    return row_composite<G>(J, R, lane, k0, valid, valid ? E[0][0] : 0.f, valid ? E[0][1] : 0.f,
+                            valid ? E[0][2] : 0.f, valid ? S[0] : 0.f, acc);
+}
+
+// Interleaved derived volume (SIG_IL3), G lanes per ray, software-pipelined:
+// the corner loads of a lane's next scan point are issued before the current
+// one is blended, classified and composited, so a row's memory latency
+// overlaps the previous row's arithmetic.  The arithmetic is that of
+// lanes_row, operation for operation.
+template <int INTERP>
+__device__ __forceinline__ void il3_locate(const DevJob& J, const RaySetup& R, int k, int (&off)[INTERP ? 8 : 1],
+                                           float (&w)[3]) {
+    const int kk = min(k, R.ke - 1);
+    const float tk = ((float)kk + 0.5f) * (float)J.step;
+    float p[3];
+    point_at(J, R, tk, p);
+    int i0[3];
+    const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (INTERP == 0) {
+            i0[a] = clampi((int)floorf(p[a]), 0, dims[a] - 1);
+            w[a] = 0.f;
+        } else {
+            const float uu = p[a] - 0.5f;
+            const float fl = floorf(uu);
+            w[a] = uu - fl;
+            i0[a] = (int)fl;
+        }
+    }
+    corner_offsets<INTERP, false>(J.src[0], dims, i0, off);
+}
+
+template <int NV>
+__device__ __forceinline__ void il3_mix(const DevJob& J, const float4* __restrict__ s_tf, const float (&v)[NV][4],
+                                        const float (&w)[3], float (&E)[3], float& S) {
+    S = 0.f;
+    E[0] = E[1] = E[2] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        float c[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) c[i] = v[i][s];
+        const float4 cl = classify(s_tf + s * kTfRows, blend<NV>(c, w));
+        const float wa = J.src[s].weight * cl.w;
+        S += wa;
+        E[0] = fmaf(wa, cl.x, E[0]);
+        E[1] = fmaf(wa, cl.y, E[1]);
+        E[2] = fmaf(wa, cl.z, E[2]);
+    }
+    mix_finish(S, E);
+}
+
+template <int INTERP, int G>
+__device__ __forceinline__ void march_lanes_il3(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                                int lane, float4& out, int& count) {
+    constexpr int NV = INTERP ? 8 : 1;
+    const int g = lane & (G - 1);
+    int off[NV];
+    float w[3], v[NV][4];
+    il3_locate<INTERP>(J, R, R.kb + g, off, w);
+    fetch_kind<K_F32x3, NV>(J.src[0], off, v);
+    RayAccum acc = {0.f, 0.f, 0.f, 0.f, 0};
+    for (int k0 = R.kb;; k0 += G) {
+        // the next row's loads (clamped to the last scan point: always in bounds)
+        int offn[NV];
+        float wn[3], vn[NV][4];
+        il3_locate<INTERP>(J, R, k0 + G + g, offn, wn);
+        fetch_kind<K_F32x3, NV>(J.src[0], offn, vn);
+        const bool valid = k0 + g < R.ke;
+        float E[3], S;
+        il3_mix<NV>(J, s_tf, v, w, E, S);
+        if (row_composite<G>(J, R, lane, k0, valid, valid ? E[0] : 0.f, valid ? E[1] : 0.f, valid ? E[2] : 0.f,
+                             valid ? S : 0.f, acc))
+            break;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[i][c] = vn[i][c];
+        w[0] = wn[0];
+        w[1] = wn[1];
+        w[2] = wn[2];
+    }
+    out = make_float4(acc.C0, acc.C1, acc.C2, acc.A);
+    count = acc.n;
+}
+
 // G lanes per ray: lane g evaluates scan points kb + g, kb + g + G, ...; each
 // row of G points is composited in order with an inclusive scan of the
 // associative front-to-back operator (C, A) o (C', A') = (C + (1-A) C',
@@ -763,6 +850,7 @@ template <int INTERP, int U, int G, int SIG, bool PS>
 __device__ __forceinline__ void march_sig(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                           int lane, float4& out, int& count) {
     if constexpr (G == 1) march_seq<INTERP, (SIG == SIG_GENERIC ? 1 : U), SIG, PS>(J, s_tf, R, out, count);
+    else if constexpr (SIG == SIG_IL3 && !PS) march_lanes_il3<INTERP, G>(J, s_tf, R, lane, out, count);
     else march_lanes<INTERP, G, SIG, PS>(J, s_tf, R, lane, out, count);
 }
 
