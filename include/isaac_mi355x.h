@@ -67,7 +67,8 @@ enum { ISAAC_VOLUME = 0, ISAAC_ISO = 1 };     /* render modes */
 
 /* isaac_render flags */
 #define ISAAC_ASYNC 1u       /* enqueue on the context stream and return without waiting */
-#define ISAAC_TIMING 2u      /* bracket the ray-casting kernel with HIP events (isaac_timing) */
+#define ISAAC_TIMING 2u      /* bracket the ray-casting kernel (single-job launches; the whole batched
+                                launch otherwise) with HIP events (isaac_timing) */
 #define ISAAC_NO_GRAPH 4u    /* batched renders: launch directly instead of replaying a hipGraph */
 #define ISAAC_DIRECT 8u      /* read and transform the sources inside the ray loop (no derived volume) */
 #define ISAAC_DERIVE 16u     /* use a derived volume whenever the sources allow it (no cost estimate) */

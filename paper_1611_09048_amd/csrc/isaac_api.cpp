@@ -874,6 +874,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
             HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipMemcpyAsync(r->dev, r->host, sizeof(DevJob) * n, hipMemcpyHostToDevice, ctx->cap_stream);
             if (e == hipSuccess) e = (hipError_t)launch_reset_counter(r->cursor, ctx->cap_stream);
+            if (e == hipSuccess) e = (hipError_t)launch_prepass(la, ctx->cap_stream);
             if (e == hipSuccess) e = (hipError_t)launch_raycast(la, ctx->cap_stream);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
@@ -914,8 +915,10 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
             int rc = launch_reset_counter(r->cursor, stream);
             if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "counter reset: %s", hipGetErrorString((hipError_t)rc));
         }
+        int rc = launch_prepass(la, stream);
+        if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "prepass launch: %s", hipGetErrorString((hipError_t)rc));
         if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
-        int rc = launch_raycast(la, stream);
+        rc = launch_raycast(la, stream);
         if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "raycast launch: %s", hipGetErrorString((hipError_t)rc));
         if (t1) HIP_TRY(ctx, hipEventRecord(t1, stream));
     }

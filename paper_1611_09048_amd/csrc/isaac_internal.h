@@ -125,6 +125,7 @@ struct LaunchArgs {
     int dense_setup;           // 1: set up every ray of the jobs' rectangles into DevJob::rays first
 };
 
+int launch_prepass(const LaunchArgs& a, void* stream);               // fill outside the rectangles, ray setup
 int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t
 int launch_reset_counter(int* counter, void* stream);
 // Pooled schedule of one job (lanes >= 2): ray setup with compaction into

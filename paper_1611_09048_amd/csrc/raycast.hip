@@ -1521,13 +1521,17 @@ KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
     }
 }
 
-int launch_raycast(const LaunchArgs& a, void* stream) {
-    // pixels outside the jobs' screen rectangles first
+int launch_prepass(const LaunchArgs& a, void* stream) {
+    // pixels outside the jobs' screen rectangles, then (optionally) the rays inside them
     hipLaunchKernelGGL(fill_outside_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0, (hipStream_t)stream,
                        a.jobs);
     if (a.dense_setup)
         hipLaunchKernelGGL(ray_setup_dense_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0,
                            (hipStream_t)stream, a.jobs);
+    return hipGetLastError();
+}
+
+int launch_raycast(const LaunchArgs& a, void* stream) {
     // dynamic LDS: one 256-entry RGBA32F table per active source of the widest job
     const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfRows * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
