@@ -52,6 +52,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "raycast_kernel_pic3_1080p_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1611_09048_amd", "csrc", "raycast.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the ray-casting kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    sha = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("kernel source sha256:")]
+    val = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("traffic_bytes_per_launch:")]
+    if not sha or not val or sha[0] != src:
+        return None
+    return int(val[0])
+
+
 def cpu_baseline(scene, gpu_counts, row_stride: int, threads: int):
     """The FP64 oracle on every row_stride-th row of the first view, on host threads."""
     import oracle
@@ -385,7 +405,7 @@ def main():
     flops = FLOPS_PER_SAMPLE * float(np.mean(fr["samples"]))
     achieved = flops / (fr["kernel_ms"] / 1e3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4), traffic=None, kernel="raycast_kernel",
+                    frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4), traffic=measured_traffic(), kernel="raycast_kernel",
                     kernel_avg_ms=round(fr["kernel_ms"], 4), algorithmic_flops_per_launch=int(flops),
                     flops_per_sample=FLOPS_PER_SAMPLE)
     # the whole frame against HBM: every stored source byte and the image once, over the frame time
