@@ -452,6 +452,38 @@ __device__ __forceinline__ void fetch_kind(const DevSource& S, const int (&off)[
     }
 }
 
+// The 8 trilinear corners (or the nearest cell) of an interleaved derived
+// volume: two per-lane base offsets (z0 and z1 planes) and the wave-uniform
+// x/y corner steps in the loads' scalar offset, so a corner costs no vector
+// address arithmetic.  Same corner order as corner_offsets.
+template <int INTERP>
+__device__ __forceinline__ void fetch_il3(const DevSource& S, const int (&i0)[3], float (&v)[INTERP ? 8 : 1][4]) {
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(S.base[0], S.num_records[0]);
+    const int sx = __builtin_amdgcn_readfirstlane(S.stride[0]);
+    const int sy = __builtin_amdgcn_readfirstlane(S.stride[1]);
+    const int sz = __builtin_amdgcn_readfirstlane(S.stride[2]);
+    const int b0 = __mul24(i0[0], sx) + __mul24(i0[1], sy) + __mul24(i0[2], sz) + S.comp_off[0];
+    auto ld3 = [&](int vo, int so, float (&d)[4]) {
+        d[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+        d[1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo + 4, so, 0));
+        d[2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo + 8, so, 0));
+        d[3] = 0.f;
+    };
+    if constexpr (INTERP == 0) {
+        ld3(b0, 0, v[0]);
+    } else {
+        const int b1 = b0 + sz;
+        ld3(b0, 0, v[0]);
+        ld3(b0, sx, v[1]);
+        ld3(b0, sy, v[2]);
+        ld3(b0, sx + sy, v[3]);
+        ld3(b1, 0, v[4]);
+        ld3(b1, sx, v[5]);
+        ld3(b1, sy, v[6]);
+        ld3(b1, sx + sy, v[7]);
+    }
+}
+
 template <int N>
 __device__ __forceinline__ float blend(const float (&c)[N], const float (&w)[3]) {
     if (N == 1) return c[0];
@@ -565,10 +597,8 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
             // the three chain outputs of a voxel are adjacent: one 12-byte load per corner
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                int off[NV];
                 float v[NV][4];
-                corner_offsets<INTERP, CL>(J.src[0], dims, i0[u], off);
-                fetch_kind<K_F32x3, NV>(J.src[0], off, v);
+                fetch_il3<INTERP>(J.src[0], i0[u], v);
 #pragma unroll
                 for (int s = 0; s < 3; ++s) {
                     float c[NV];
@@ -753,18 +783,15 @@ __device__ __forceinline__ bool lanes_row(const DevJob& J, const float4* __restr
 // overlaps the previous row's arithmetic.  The arithmetic is that of
 // lanes_row, operation for operation.
 template <int INTERP>
-__device__ __forceinline__ void il3_locate(const DevJob& J, const RaySetup& R, int k, int (&off)[INTERP ? 8 : 1],
-                                           float (&w)[3]) {
+__device__ __forceinline__ void il3_locate(const DevJob& J, const RaySetup& R, int k, int (&i0)[3], float (&w)[3]) {
     const int kk = min(k, R.ke - 1);
     const float tk = ((float)kk + 0.5f) * (float)J.step;
     float p[3];
     point_at(J, R, tk, p);
-    int i0[3];
-    const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (INTERP == 0) {
-            i0[a] = clampi((int)floorf(p[a]), 0, dims[a] - 1);
+            i0[a] = clampi((int)floorf(p[a]), 0, J.dims[a] - 1);
             w[a] = 0.f;
         } else {
             const float uu = p[a] - 0.5f;
@@ -773,7 +800,6 @@ __device__ __forceinline__ void il3_locate(const DevJob& J, const RaySetup& R, i
             i0[a] = (int)fl;
         }
     }
-    corner_offsets<INTERP, false>(J.src[0], dims, i0, off);
 }
 
 template <int NV>
@@ -801,17 +827,17 @@ __device__ __forceinline__ void march_lanes_il3(const DevJob& J, const float4* _
                                                 int lane, float4& out, int& count) {
     constexpr int NV = INTERP ? 8 : 1;
     const int g = lane & (G - 1);
-    int off[NV];
+    int i0[3];
     float w[3], v[NV][4];
-    il3_locate<INTERP>(J, R, R.kb + g, off, w);
-    fetch_kind<K_F32x3, NV>(J.src[0], off, v);
+    il3_locate<INTERP>(J, R, R.kb + g, i0, w);
+    fetch_il3<INTERP>(J.src[0], i0, v);
     RayAccum acc = {0.f, 0.f, 0.f, 0.f, 0};
     for (int k0 = R.kb;; k0 += G) {
         // the next row's loads (clamped to the last scan point: always in bounds)
-        int offn[NV];
+        int i0n[3];
         float wn[3], vn[NV][4];
-        il3_locate<INTERP>(J, R, k0 + G + g, offn, wn);
-        fetch_kind<K_F32x3, NV>(J.src[0], offn, vn);
+        il3_locate<INTERP>(J, R, k0 + G + g, i0n, wn);
+        fetch_il3<INTERP>(J.src[0], i0n, vn);
         const bool valid = k0 + g < R.ke;
         float E[3], S;
         il3_mix<NV>(J, s_tf, v, w, E, S);
