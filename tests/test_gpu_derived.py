@@ -148,12 +148,13 @@ def test_pairs_loop_parity(ctx, lanes):
         for m in (0, 4):
             ctx.set_tile_shape(cls, 64 // lanes if lanes >= 8 else 8, 2, 2, lanes, m, 0)
             for i, sc in enumerate((base, opaque)):
-                for ert in (0.0, NO_TERMINATION):
-                    img, cnt = device.render_scene(ctx, sc, volume_id=9, flags=DERIVE, ert_threshold=ert)
+                for ert in (None, NO_TERMINATION):
+                    kw = {} if ert is None else dict(ert_threshold=ert)
+                    img, cnt = device.render_scene(ctx, sc, volume_id=9, flags=DERIVE, **kw)
                     rec = oracle.render(sc, ert_threshold=ert, threads=8)
                     compare(img.reshape(-1, 4), cnt.reshape(-1), rec,
                             label=f"pairs lanes={lanes} min_waves={m} scene={i} ert={ert}")
-                    again, cnt2 = device.render_scene(ctx, sc, volume_id=9, flags=DERIVE, ert_threshold=ert)
+                    again, cnt2 = device.render_scene(ctx, sc, volume_id=9, flags=DERIVE, **kw)
                     assert np.array_equal(img, again) and np.array_equal(cnt, cnt2)
     finally:
         ctx.set_tile_shape(cls, *old)
