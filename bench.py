@@ -45,7 +45,7 @@ FP32_VALU_PEAK_TFLOPS = 78.6
 FLOPS_PER_SAMPLE = 150
 TUNED = os.path.join(ROOT, "paper_1611_09048_amd", "tuned_gfx950.json")
 # candidates the bench tunes over when its cache has no entry
-QUICK = dict(lanes=(4, 8, 16, 32), wave_ws=(2, 4, 8, 16), waves_xs=(1, 2, 4), unrolls=(1, 2), min_waves=(0, 4))
+QUICK = dict(lanes=(4, 8, 16, 32), wave_ws=(2, 4, 8, 16), waves_xs=(1, 2, 4), unrolls=(1,), min_waves=(0, 4))
 
 
 def log(*a):

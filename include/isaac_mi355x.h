@@ -242,13 +242,11 @@ isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count);
  *   wave_w, a power of two in [1, 64/lanes_per_ray]: a wave's rays form a
  *     wave_w x (64/lanes_per_ray/wave_w) pixel block;
  *   waves_x in {1,2,4}: the 4 waves of a workgroup are waves_x x 4/waves_x;
- *   unroll in {1,2}: with one lane per ray, scan points whose source reads
- *     are issued together; with 4, 8 or 16 lanes per ray, consecutive scan
- *     points per lane in a row (the three-scalar derived-volume loop
- *     composites them as a pair before the group scan; other loops ignore it);
+ *   unroll in {1,2} (one lane per ray only): scan points whose source reads
+ *     are issued together;
  *   min_waves in {0,4}: 4 selects the kernel variant compiled to keep at
- *     least 4 waves resident per SIMD (not with lanes_per_ray 2, 32 or 64,
- *     nor with unroll 2 and one lane per ray);
+ *     least 4 waves resident per SIMD (not with lanes_per_ray 2, 32, 64 or
+ *     unroll 2);
  *   pooled in {0,1} (lanes_per_ray 2..16): a render call's single-job
  *     launches first set up every pixel's ray and compact the rays that keep
  *     scan points into a list, then resident waves hand those rays to lane

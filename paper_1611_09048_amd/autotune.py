@@ -42,9 +42,9 @@ def candidates(unrolls: Sequence[int] = UNROLL, lanes: Sequence[int] = LANES, wa
     The pooled schedule ignores the tile shape, so it is tried once per lane count."""
     out = []
     for g in lanes:
-        for u in (unrolls if g in (1, 4, 8, 16) else (1,)):
+        for u in (unrolls if g == 1 else (1,)):
             for m in min_waves:
-                if m and (g == 2 or g >= 32 or (u == 2 and g == 1)):
+                if m and (g == 2 or g >= 32 or u == 2):
                     continue
                 if 0 in pooled:
                     for w in wave_ws:

@@ -509,7 +509,7 @@ int32_t signature_of(const DevJob& dj) {
 // are cleared by a fill kernel.
 void set_tiles(DevJob& dj, int lanes, int unroll) {
     dj.lanes = lanes;
-    dj.unroll = (lanes == 1 || lanes == 4 || lanes == 8 || lanes == 16) ? unroll : 1;
+    dj.unroll = lanes > 1 ? 1 : unroll;
     const int rays = 64 / lanes;
     if (dj.wave_w > rays) dj.wave_w = rays;
     const int tw = dj.wave_w * dj.waves_x, th = (rays / dj.wave_w) * (4 / dj.waves_x);
@@ -799,8 +799,8 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     int lanes = 1, unroll = 1, hint = 0;
     for (const DevJob& dj : djs) lanes = std::max(lanes, (int)dj.lanes);
     for (const DevJob& dj : djs) hint = std::max(hint, (int)dj.waves_hint);
-    for (const DevJob& dj : djs) unroll = std::max(unroll, (int)dj.unroll);
-    if (!(lanes == 1 || lanes == 4 || lanes == 8 || lanes == 16)) unroll = 1;
+    if (lanes == 1)
+        for (const DevJob& dj : djs) unroll = std::max(unroll, (int)dj.unroll);
     int tiles = 0;
     for (int i = 0; i < n; ++i) {
         r->host[i] = djs[i];
@@ -824,7 +824,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     la.max_src = std::max(1, max_src);
     la.unroll = unroll;
     la.lanes = lanes;
-    la.waves_hint = (lanes == 2 || lanes >= 32 || (unroll > 1 && lanes == 1)) ? 0 : hint;
+    la.waves_hint = (lanes == 2 || lanes >= 32 || unroll > 1) ? 0 : hint;
     la.sig = djs[0].sig;
     for (const DevJob& dj : djs)
         if (dj.sig != la.sig) la.sig = -1;
@@ -1465,9 +1465,8 @@ isaac_status isaac_set_tile_shape(isaac_context* ctx, int size_class, int wave_w
     const bool lanes_ok = g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64;
     const bool ww_ok = wave_w >= 1 && wave_w <= 64 && (wave_w & (wave_w - 1)) == 0 && lanes_ok && wave_w <= 64 / g;
     if (size_class < 0 || size_class > 15 || !ww_ok || (waves_x != 1 && waves_x != 2 && waves_x != 4) ||
-        (unroll != 1 && unroll != 2) || (unroll == 2 && g != 1 && g != 4 && g != 8 && g != 16) ||
-        (min_waves != 0 && min_waves != 4) || (min_waves == 4 && (g == 2 || g >= 32 || (unroll == 2 && g == 1))) ||
-        (pooled != 0 && pooled != 1) || (pooled == 1 && unroll != 1) ||
+        (unroll != 1 && unroll != 2) || (g > 1 && unroll != 1) || (min_waves != 0 && min_waves != 4) ||
+        (min_waves == 4 && (g == 2 || g >= 32 || unroll == 2)) || (pooled != 0 && pooled != 1) ||
         (pooled == 1 && (g < 2 || g > 16)))
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "invalid tile shape");
     ctx->shapes[size_class] = TileShape{wave_w, waves_x, unroll, g, min_waves == 4 ? 1 : 0, pooled};

@@ -863,80 +863,6 @@ __device__ __forceinline__ void march_lanes_il3(const DevJob& J, const float4* _
     count = acc.n;
 }
 
-// Two consecutive scan points per lane (rows of 2G points; interleaved
-// derived volume): lane g composites points k0 + 2g and k0 + 2g + 1 into one
-// pair, and the group scan runs over the pairs, so the scan and the selection
-// cost half as much per point.  Termination stays exact: every lane computes
-// the cumulative opacity after each of its two points from the exclusive
-// prefix of the pairs before it, and the ray stops at the first point that
-// reaches ert.
-template <int INTERP, int G>
-__device__ __forceinline__ void march_lanes_il3_pairs(const DevJob& J, const float4* __restrict__ s_tf,
-                                                      const RaySetup& R, int lane, float4& out, int& count) {
-    constexpr int NV = INTERP ? 8 : 1;
-    const int g = lane & (G - 1);
-    RayAccum acc = {0.f, 0.f, 0.f, 0.f, 0};
-    for (int k0 = R.kb;; k0 += 2 * G) {
-        const int ka = k0 + 2 * g;
-        const bool va = ka < R.ke, vb = ka + 1 < R.ke;
-        float Ea[3], Sa, Eb[3], Sb;
-        {
-            int ia[3], ib[3];
-            float wa[3], wb[3], v[NV][4], u[NV][4];
-            il3_locate<INTERP>(J, R, ka, ia, wa);
-            fetch_il3<INTERP>(J.src[0], ia, v);
-            il3_locate<INTERP>(J, R, ka + 1, ib, wb);
-            fetch_il3<INTERP>(J.src[0], ib, u);
-            il3_mix<NV>(J, s_tf, v, wa, Ea, Sa);
-            il3_mix<NV>(J, s_tf, u, wb, Eb, Sb);
-        }
-        if (!va) {
-            Ea[0] = Ea[1] = Ea[2] = Sa = 0.f;
-        }
-        if (!vb) {
-            Eb[0] = Eb[1] = Eb[2] = Sb = 0.f;
-        }
-        // the pair, front to back
-        const float ta = 1.f - Sa;
-        float c0 = fmaf(ta, Eb[0], Ea[0]), c1 = fmaf(ta, Eb[1], Ea[1]), c2 = fmaf(ta, Eb[2], Ea[2]);
-        float a = fmaf(ta, Sb, Sa);
-        group_scan<G>(lane, c0, c1, c2, a);
-        // exclusive prefix: the inclusive value of the lane below (none for the group's first lane)
-        const int below = lane > 0 ? lane - 1 : 0;
-        float x0 = __shfl(c0, below, 64), x1 = __shfl(c1, below, 64), x2 = __shfl(c2, below, 64);
-        float xa = __shfl(a, below, 64);
-        if (g == 0) x0 = x1 = x2 = xa = 0.f;
-        // running state after point a (prefix through a) and after point b (inclusive)
-        const float T = 1.f - acc.A;
-        const float tx = 1.f - xa;
-        const float pa0 = fmaf(tx, Ea[0], x0), pa1 = fmaf(tx, Ea[1], x1), pa2 = fmaf(tx, Ea[2], x2);
-        const float paa = fmaf(tx, Sa, xa);
-        const float A_a = fmaf(T, paa, acc.A), A_b = fmaf(T, a, acc.A);
-        const bool hit_a = va && A_a >= J.ert, hit_b = vb && A_b >= J.ert;
-        const unsigned long long m = __ballot(hit_a || hit_b);
-        constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull);
-        const unsigned long long bits = (m >> (lane & ~(G - 1))) & kGroupMask;
-        const bool stop = bits != 0;
-        const int nvalid = min(2 * G, R.ke - k0);
-        const int sel = stop ? __builtin_ctzll(bits) : (nvalid - 1) >> 1;
-        // each lane offers its state at the point where it would stop
-        const bool at_a = hit_a;
-        const float s0 = at_a ? fmaf(T, pa0, acc.C0) : fmaf(T, c0, acc.C0);
-        const float s1 = at_a ? fmaf(T, pa1, acc.C1) : fmaf(T, c1, acc.C1);
-        const float s2 = at_a ? fmaf(T, pa2, acc.C2) : fmaf(T, c2, acc.C2);
-        const float sa = at_a ? A_a : A_b;
-        const int used = stop ? 2 * sel + (__shfl((int)at_a, sel, G) ? 1 : 2) : nvalid;
-        acc.n += used;
-        acc.C0 = __shfl(s0, sel, G);
-        acc.C1 = __shfl(s1, sel, G);
-        acc.C2 = __shfl(s2, sel, G);
-        acc.A = __shfl(sa, sel, G);
-        if (stop || k0 + 2 * G >= R.ke) break;
-    }
-    out = make_float4(acc.C0, acc.C1, acc.C2, acc.A);
-    count = acc.n;
-}
-
 // G lanes per ray: lane g evaluates scan points kb + g, kb + g + G, ...; each
 // row of G points is composited in order with an inclusive scan of the
 // associative front-to-back operator (C, A) o (C', A') = (C + (1-A) C',
@@ -957,7 +883,6 @@ template <int INTERP, int U, int G, int SIG, bool PS>
 __device__ __forceinline__ void march_sig(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                           int lane, float4& out, int& count) {
     if constexpr (G == 1) march_seq<INTERP, (SIG == SIG_GENERIC ? 1 : U), SIG, PS>(J, s_tf, R, out, count);
-    else if constexpr (SIG == SIG_IL3 && U == 2) march_lanes_il3_pairs<INTERP, G>(J, s_tf, R, lane, out, count);
     else if constexpr (SIG == SIG_IL3 && !PS) march_lanes_il3<INTERP, G>(J, s_tf, R, lane, out, count);
     else march_lanes<INTERP, G, SIG, PS>(J, s_tf, R, lane, out, count);
 }
@@ -1594,13 +1519,7 @@ using KernelFn = void (*)(const DevJob*, const float4*, int*, int, int, int);
 
 template <int SIGK>
 KernelFn pick_specialized(int unroll, int lanes, int hint) {
-    if constexpr (SIGK == SIG_IL3) {
-        // two points per lane with lanes per ray (the pairs loop)
-        if (unroll >= 2 && lanes == 16) return hint ? raycast_kernel<2, 16, 4, SIGK> : raycast_kernel<2, 16, 0, SIGK>;
-        if (unroll >= 2 && lanes == 8) return hint ? raycast_kernel<2, 8, 4, SIGK> : raycast_kernel<2, 8, 0, SIGK>;
-        if (unroll >= 2 && lanes == 4) return hint ? raycast_kernel<2, 4, 4, SIGK> : raycast_kernel<2, 4, 0, SIGK>;
-    }
-    if (unroll >= 2 && lanes == 1) return raycast_kernel<2, 1, 0, SIGK>;
+    if (unroll >= 2) return raycast_kernel<2, 1, 0, SIGK>;
     switch (lanes) {
     case 64: return raycast_kernel<1, 64, 0, SIGK>;
     case 32: return raycast_kernel<1, 32, 0, SIGK>;

@@ -11,7 +11,6 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.oracle import NO_TERMINATION
 from parity import compare, log
 from scenes import configs, make_source, relayout
 
@@ -131,30 +130,3 @@ def test_derived_skips_clipped_voxels_only(ctx):
                      sources=[dataclasses.replace(s, iso=v) for s, v in zip(base.sources, (1.0, 0.2, float("nan")))])
     a, b = both(ctx, iso, vid=8)
     assert_same(a, b, "heavy clip iso")
-
-
-@pytest.mark.parametrize("lanes", [4, 8, 16])
-def test_pairs_loop_parity(ctx, lanes):
-    """Two scan points per lane (unroll 2 with lanes per ray, the derived
-    three-scalar loop) against the oracle: normal and opaque transfer functions
-    (termination inside a pair at either point), with and without termination."""
-    from paper_1611_09048_amd import DERIVE, autotune, device
-    base = configs.pic3(n=40, width=128, height=96, direction=(0.4, -0.7, 0.6))
-    rng = np.random.default_rng(lanes)
-    opaque = base.with_(sources=[dataclasses.replace(s, tf=configs.random_tf(rng, 6, 0.35)) for s in base.sources])
-    cls = autotune.size_class(base.width, base.height)
-    old = ctx.get_tile_shape(cls)
-    try:
-        for m in (0, 4):
-            ctx.set_tile_shape(cls, 64 // lanes if lanes >= 8 else 8, 2, 2, lanes, m, 0)
-            for i, sc in enumerate((base, opaque)):
-                for ert in (None, NO_TERMINATION):
-                    kw = {} if ert is None else dict(ert_threshold=ert)
-                    img, cnt = device.render_scene(ctx, sc, volume_id=9, flags=DERIVE, **kw)
-                    rec = oracle.render(sc, ert_threshold=ert, threads=8)
-                    compare(img.reshape(-1, 4), cnt.reshape(-1), rec,
-                            label=f"pairs lanes={lanes} min_waves={m} scene={i} ert={ert}")
-                    again, cnt2 = device.render_scene(ctx, sc, volume_id=9, flags=DERIVE, **kw)
-                    assert np.array_equal(img, again) and np.array_equal(cnt, cnt2)
-    finally:
-        ctx.set_tile_shape(cls, *old)
