@@ -189,12 +189,12 @@ def code_lengths(freq: List[int]) -> List[int]:
         while others[c2] >= 0:
             c2 = others[c2]
             size[c2] += 1
-    bits = [0] * 33
+    bits = [0] * 258                           # a depth can exceed 32 for very skewed counts
     for v in range(257):
         if size[v]:
             bits[size[v]] += 1
     # limit to 16 bits: move pairs of the longest codes up
-    for i in range(32, 16, -1):
+    for i in range(max(size), 16, -1):
         while bits[i] > 0:
             j = i - 2
             while bits[j] == 0:

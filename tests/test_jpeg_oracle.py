@@ -136,7 +136,8 @@ def pin_huffman_lengths(mod):
     fib = [1, 1]
     while len(fib) < 40:
         fib.append(fib[-1] + fib[-2])
-    cases = [list(rng.integers(0, 1000, size=256)), [0] * 256, fib + [0] * 216]
+    skew = [2 ** k for k in range(45)] + [0] * 211   # Huffman depth 45 before the 16-bit limit
+    cases = [list(rng.integers(0, 1000, size=256)), [0] * 256, fib + [0] * 216, skew]
     cases[1][7] = 5
     for freq in cases:
         lengths = mod.code_lengths(freq)
@@ -174,7 +175,7 @@ MUTANTS = [
     ("dct_transposed", "    return (m @ t + 8192) >> 14", "    return ((m @ t + 8192) >> 14).T"),
     ("negative_extra_bits", "diff if diff >= 0 else diff + (1 << s) - 1", "diff if diff >= 0 else -diff"),
     ("eob_missing", "    if last < 63:\n        syms.append", "    if False:\n        syms.append"),
-    ("no_length_limit", "    for i in range(32, 16, -1):", "    for i in range(0):"),
+    ("no_length_limit", "    for i in range(max(size), 16, -1):", "    for i in range(0):"),
     ("reserved_kept", "    bits[i] -= 1\n", "    bits[i] -= 0\n"),
     ("quantize_truncates", "    mag = (np.abs(f) + q // 2) // q", "    mag = np.abs(f) // q"),
 ]
