@@ -229,6 +229,31 @@ isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const
 isaac_status isaac_encode_rgba8(isaac_context* ctx, const float* rgba, int width, int height,
                                 const float* background, unsigned char* out, unsigned flags);
 
+/* JPEG compression of an RGBA8 frame, the form in which the root rank sends
+ * the composited image to the server (Sec. 3.4).  The paper leaves the
+ * encoder open; this one writes baseline sequential JPEG (JFIF 1.01):
+ *  - colour: Y, Cb, Cr from R, G, B (alpha ignored) with the JFIF weights in
+ *    16-bit fixed point, each rounded half up by a shift; no subsampling;
+ *  - 8x8 blocks in raster order, the frame extended by repeating its last
+ *    column and row; samples minus 128;
+ *  - forward DCT with the cosine matrix rounded to 12 fractional bits, the
+ *    row pass keeping 2 fractional bits, both passes rounded half up by shifts;
+ *  - the example tables of the JPEG standard (Annex K) scaled by quality
+ *    (1..100; 5000/q percent below 50, else 200 - 2q), quotients rounded half
+ *    away from zero;
+ *  - four Huffman tables (DC and AC, luma and chroma) built for this frame
+ *    from its symbol counts by the procedure of Annex K.2 (ties to the larger
+ *    symbol value, lengths limited to 16 bits), canonical codes;
+ *  - last byte padded with 1 bits, 0x00 after every 0xFF data byte.
+ * rgba8: device, width*height*4 bytes, row 0 on top; width and height in
+ * 1..65535.  out: host, capacity bytes; *out_size receives the stream's size,
+ * also when capacity is too small (then ISAAC_ERR_INVALID_ARGUMENT and out is
+ * not written).  The stream is a fixed function of (pixels, quality).  Runs on
+ * the context stream (ordered after earlier work there) and returns when the
+ * stream is in out; scratch memory is kept by the context between calls. */
+isaac_status isaac_encode_jpeg(isaac_context* ctx, const unsigned char* rgba8, int width, int height, int quality,
+                               unsigned char* out, size_t capacity, size_t* out_size);
+
 /* Sum and count of the kernel durations of ISAAC_TIMING renders since the
  * last call (waits for them), then resets. */
 isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count);
@@ -289,6 +314,12 @@ isaac_status isaac_read_image(isaac_context* ctx, uint64_t ticket, float* host_r
  * background: host rgb in [0,1] or NULL. */
 isaac_status isaac_read_image_rgba8(isaac_context* ctx, uint64_t ticket, const float* background,
                                     unsigned char* host_rgba8);
+
+/* Encode a ticket's image to RGBA8 as isaac_read_image_rgba8 does, then to
+ * JPEG as isaac_encode_jpeg does (waiting for both): what the root rank sends
+ * to the server (Sec. 3.4). */
+isaac_status isaac_read_image_jpeg(isaac_context* ctx, uint64_t ticket, const float* background, int quality,
+                                   unsigned char* out, size_t capacity, size_t* out_size);
 
 /* Return the image memory of a completed (or not yet complete: waits) ticket. */
 isaac_status isaac_release(isaac_context* ctx, uint64_t ticket);

@@ -73,7 +73,7 @@ class RenderDesc(ctypes.Structure):
 EXPORTS = ["isaac_init", "isaac_destroy", "isaac_last_error", "isaac_init_error", "isaac_set_sources",
            "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_composite", "isaac_encode_rgba8",
            "isaac_timing", "isaac_set_tile_shape", "isaac_get_tile_shape", "isaac_submit", "isaac_submit_batch",
-           "isaac_poll", "isaac_release", "isaac_read_image", "isaac_read_image_rgba8", "isaac_serving_usage",
+           "isaac_poll", "isaac_release", "isaac_read_image", "isaac_read_image_rgba8", "isaac_encode_jpeg", "isaac_read_image_jpeg", "isaac_serving_usage",
            "isaac_check_functor_chain", "isaac_version"]
 
 _lib = None
@@ -109,6 +109,10 @@ def load(path: Optional[str] = None):
     lib.isaac_encode_rgba8.argtypes = [c_ctx, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_uint]
     lib.isaac_read_image_rgba8.argtypes = [c_ctx, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
+    lib.isaac_encode_jpeg.argtypes = [c_ctx, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    lib.isaac_read_image_jpeg.argtypes = [c_ctx, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     lib.isaac_set_tile_shape.argtypes = [c_ctx] + [ctypes.c_int] * 7
     lib.isaac_get_tile_shape.argtypes = [c_ctx, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 6
     lib.isaac_submit.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.POINTER(ctypes.c_uint64)]
@@ -218,6 +222,26 @@ class Context:
         bg = (ctypes.c_float * 3)(*map(float, background)) if background is not None else None
         self._check(self.lib.isaac_encode_rgba8(self.h, rgba_ptr, width, height, bg, out_ptr, flags))
 
+    def _jpeg_call(self, call, width: int, height: int) -> bytes:
+        # a first guess of the stream size; on a too small buffer the library reports the size it needs
+        size = ctypes.c_size_t(0)
+        cap = width * height * 4 + 4096
+        for _ in range(2):
+            buf = ctypes.create_string_buffer(cap)
+            rc = call(buf, cap, size)
+            if rc == 0:
+                return buf.raw[: size.value]
+            if rc != -1 or size.value <= cap:
+                break
+            cap = size.value
+        self._check(rc)
+        raise IsaacError(rc, "jpeg encode failed")
+
+    def encode_jpeg(self, rgba8_ptr: int, width: int, height: int, quality: int = 90) -> bytes:
+        """JPEG bytes of a device RGBA8 frame (rows top to bottom, alpha ignored)."""
+        return self._jpeg_call(lambda buf, cap, size: self.lib.isaac_encode_jpeg(
+            self.h, rgba8_ptr, width, height, quality, buf, cap, ctypes.byref(size)), width, height)
+
     def timing(self):
         ms, n = ctypes.c_double(), ctypes.c_int()
         self._check(self.lib.isaac_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
@@ -266,6 +290,12 @@ class Context:
         bg = (ctypes.c_float * 3)(*map(float, background)) if background is not None else None
         self._check(self.lib.isaac_read_image_rgba8(self.h, ctypes.c_uint64(ticket), bg, out.ctypes.data))
         return out
+
+    def read_image_jpeg(self, ticket: int, width: int, height: int, quality: int = 90, background=None) -> bytes:
+        """JPEG bytes of a ticket's image (encoded to RGBA8 over `background`, then compressed, on the device)."""
+        bg = (ctypes.c_float * 3)(*map(float, background)) if background is not None else None
+        return self._jpeg_call(lambda buf, cap, size: self.lib.isaac_read_image_jpeg(
+            self.h, ctypes.c_uint64(ticket), bg, quality, buf, cap, ctypes.byref(size)), width, height)
 
     def serving_usage(self):
         u, b, n = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()

@@ -23,6 +23,7 @@
 
 #include "../../include/isaac_mi355x.h"
 #include "isaac_internal.h"
+#include "jpeg_internal.h"
 
 using namespace isaac;
 
@@ -245,6 +246,7 @@ struct Ticket {
     uint64_t id;
     float* out = nullptr;
     size_t bytes = 0;
+    int width = 0, height = 0;
     hipEvent_t ev = nullptr;
     bool done = false;
 };
@@ -285,7 +287,8 @@ struct isaac_context {
     std::multimap<size_t, float*> image_cache;
     size_t cached = 0;
     uint64_t next_ticket = 1;
-    void* enc_buf = nullptr;           // RGBA8 staging of isaac_read_image_rgba8
+    void* enc_buf = nullptr;           // RGBA8 staging of isaac_read_image_rgba8 / _jpeg
+    isaac::JpegWork* jpeg = nullptr;   // JPEG encoder scratch, created on first use
     size_t enc_bytes = 0;
     void* pool_rays = nullptr;         // compacted rays of the pooled schedule
     size_t pool_bytes = 0;
@@ -1276,6 +1279,7 @@ void isaac_destroy(isaac_context* ctx) {
     for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
     if (ctx->tf_pool) hipFree(ctx->tf_pool);
     if (ctx->enc_buf) hipFree(ctx->enc_buf);
+    isaac::jpeg_work_destroy(ctx->jpeg);
     if (ctx->pool_rays) hipFree(ctx->pool_rays);
     if (ctx->pool_counters) hipFree(ctx->pool_counters);
     for (hipStream_t s : ctx->serve_streams) hipStreamDestroy(s);
@@ -1438,6 +1442,18 @@ isaac_status isaac_encode_rgba8(isaac_context* ctx, const float* rgba, int width
     return ISAAC_OK;
 }
 
+isaac_status isaac_encode_jpeg(isaac_context* ctx, const unsigned char* rgba8, int width, int height, int quality,
+                               unsigned char* out, size_t capacity, size_t* out_size) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!ctx->jpeg) ctx->jpeg = isaac::jpeg_work_create();
+    char msg[256] = {0};
+    const int rc = isaac::jpeg_encode(ctx->jpeg, rgba8, width, height, quality, ctx->stream, out, capacity, out_size,
+                                      msg, sizeof msg);
+    if (rc) return set_err(ctx, (isaac_status)rc, "jpeg: %s", msg);
+    return ISAAC_OK;
+}
+
 isaac_status isaac_timing(isaac_context* ctx, double* total_ms, int* count) {
     isaac_status st = check_ctx(ctx);
     if (st) return st;
@@ -1519,6 +1535,8 @@ isaac_status isaac_submit_batch(isaac_context* ctx, const isaac_render_desc* job
         Ticket t;
         t.id = ctx->next_ticket++;
         t.bytes = (size_t)jobs[i].width * jobs[i].height * 4 * sizeof(float);
+        t.width = jobs[i].width;
+        t.height = jobs[i].height;
         auto it = ctx->image_cache.find(t.bytes);
         if (it != ctx->image_cache.end()) {
             t.out = it->second;
@@ -1642,6 +1660,34 @@ isaac_status isaac_read_image_rgba8(isaac_context* ctx, uint64_t ticket, const f
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     t.done = true;
     return ISAAC_OK;
+}
+
+isaac_status isaac_read_image_jpeg(isaac_context* ctx, uint64_t ticket, const float* background, int quality,
+                                   unsigned char* out, size_t capacity, size_t* out_size) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) return set_err(ctx, ISAAC_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (background)
+        for (int c = 0; c < 3; ++c)
+            if (!(background[c] >= 0.f && background[c] <= 1.f))
+                return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "background channel %d must lie in [0,1]", c);
+    Ticket& t = it->second;
+    const int64_t n = (int64_t)(t.bytes / 16);
+    if ((size_t)n * 4 > ctx->enc_bytes) {
+        if (ctx->enc_buf) HIP_TRY(ctx, hipFree(ctx->enc_buf));
+        ctx->enc_buf = nullptr;
+        ctx->enc_bytes = 0;
+        HIP_TRY(ctx, hipMalloc(&ctx->enc_buf, (size_t)n * 4));
+        ctx->enc_bytes = (size_t)n * 4;
+    }
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, t.ev, 0));
+    int rc = launch_encode_rgba8(t.out, n, background, static_cast<unsigned char*>(ctx->enc_buf), ctx->stream);
+    if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "encode launch: %s", hipGetErrorString((hipError_t)rc));
+    st = isaac_encode_jpeg(ctx, static_cast<const unsigned char*>(ctx->enc_buf), t.width, t.height, quality, out,
+                           capacity, out_size);
+    if (st == ISAAC_OK) t.done = true;
+    return st;
 }
 
 isaac_status isaac_serving_usage(isaac_context* ctx, size_t* used, size_t* budget, int* inflight) {

@@ -1,0 +1,121 @@
+"""JPEG compression on the GPU, byte for byte against the JPEG oracle.
+
+Every coefficient, symbol count, Huffman table and bit of the stream is a
+fixed integer function of the pixels and the quality, so the device stream
+must equal oracle/jpeg.py's exactly: on tiny and ragged frames (edge
+replication), on noise (many 0xFF bytes to stuff, long codes), on constant
+frames (one-symbol tables), at qualities 1..100, and on full 1080p frames.
+"""
+
+import io
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import jpeg
+from parity import log
+from scenes import configs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1611_09048_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(device=0)
+    yield c
+    c.close()
+
+
+def frame(kind, h, w, seed=0):
+    rng = np.random.default_rng(seed + 1000 * h + w)
+    img = np.empty((h, w, 4), np.uint8)
+    if kind == "noise":
+        img[...] = rng.integers(0, 256, size=(h, w, 4))
+    elif kind == "constant":
+        img[...] = rng.integers(0, 256, size=4)
+    else:
+        y, x = np.mgrid[0:h, 0:w]
+        for c in range(3):
+            a, b, p = rng.uniform(3, 40), rng.uniform(3, 40), rng.uniform(0, 6)
+            img[..., c] = np.clip(128 + 110 * np.sin(x / a + p) * np.cos(y / b), 0, 255).astype(np.uint8)
+        img[..., 3] = rng.integers(0, 256, size=(h, w))
+        img[::7, ::5, :3] = rng.integers(0, 256, size=img[::7, ::5, :3].shape)   # sharp detail
+    return img
+
+
+def device_jpeg(ctx, img, quality):
+    import torch
+    d = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    return ctx.encode_jpeg(d.data_ptr(), img.shape[1], img.shape[0], quality)
+
+
+def check(got, want, label):
+    same = got == want
+    if not same:
+        n = min(len(got), len(want))
+        first = next((i for i in range(n) if got[i] != want[i]), n)
+        log(f"{label}: {len(got)} vs {len(want)} bytes, first difference at byte {first}")
+    else:
+        log(f"{label}: {len(got)} bytes identical")
+    assert same
+
+
+@pytest.mark.parametrize("quality", [1, 50, 90, 100])
+@pytest.mark.parametrize("kind", ["smooth", "noise", "constant"])
+@pytest.mark.parametrize("shape", [(1, 1), (7, 13), (17, 9), (8, 8), (45, 61), (64, 128)])
+def test_jpeg_bit_exact_small(ctx, shape, kind, quality):
+    img = frame(kind, *shape)
+    check(device_jpeg(ctx, img, quality), jpeg.encode(img, quality), f"jpeg {shape} {kind} q{quality}")
+
+
+@pytest.mark.parametrize("shape,kind,quality", [((1080, 1920), "smooth", 90), ((1080, 1920), "noise", 97),
+                                                ((1079, 1917), "smooth", 75)])
+def test_jpeg_bit_exact_1080p(ctx, shape, kind, quality):
+    img = frame(kind, *shape)
+    got = device_jpeg(ctx, img, quality)
+    check(got, jpeg.encode(img, quality), f"jpeg {shape} {kind} q{quality}")
+    PIL = pytest.importorskip("PIL.Image")
+    dec = np.asarray(PIL.open(io.BytesIO(got)).convert("RGB"))
+    assert dec.shape == (shape[0], shape[1], 3)
+
+
+def test_jpeg_calls_in_a_row(ctx):
+    """Scratch buffers are reused: a large frame, a smaller one, another quality, the first again."""
+    big = frame("smooth", 200, 300, seed=1)
+    small = frame("noise", 20, 24, seed=2)
+    for img, q in ((big, 80), (small, 80), (small, 30), (big, 80)):
+        check(device_jpeg(ctx, img, q), jpeg.encode(img, q), f"jpeg sequence {img.shape[:2]} q{q}")
+
+
+def test_served_image_as_jpeg(ctx):
+    """isaac_read_image_jpeg equals the oracle's JPEG of the oracle's RGBA8 encode of the served image."""
+    from paper_1611_09048_amd import device
+    sc = configs.pic3(n=32, width=120, height=90)
+    vol = device.upload_volume(ctx, sc, 3)
+    t = ctx.submit(device.render_job(sc, 3, device.new_image(sc)))
+    f32 = ctx.read_image(t, np.zeros((sc.height, sc.width, 4), dtype=np.float32))
+    for bg, q in ((None, 90), ((1.0, 1.0, 1.0), 60)):
+        got = ctx.read_image_jpeg(t, sc.width, sc.height, q, bg)
+        check(got, jpeg.encode(oracle.encode_rgba8(f32, bg), q), f"served jpeg bg={bg} q{q}")
+    ctx.release(t)
+    del vol
+
+
+def test_jpeg_rejects_bad_arguments(ctx):
+    import ctypes
+    import torch
+    from paper_1611_09048_amd import binding
+    a = torch.zeros((16, 16, 4), dtype=torch.uint8, device="cuda")
+    for w, h, q in ((16, 16, 0), (16, 16, 101), (0, 16, 50), (16, 0, 50), (65536, 1, 50)):
+        with pytest.raises(binding.IsaacError) as e:
+            ctx.encode_jpeg(a.data_ptr(), w, h, q)
+        assert e.value.code == -1
+    # too small a buffer: the call fails and reports the size it needs
+    size = ctypes.c_size_t(0)
+    buf = ctypes.create_string_buffer(8)
+    rc = ctx.lib.isaac_encode_jpeg(ctx.h, a.data_ptr(), 16, 16, 50, buf, 8, ctypes.byref(size))
+    assert rc == -1 and size.value == len(jpeg.encode(np.zeros((16, 16, 4), np.uint8), 50))
