@@ -323,6 +323,31 @@ def encode(ctx, width: int, height: int, reps: int = 50):
     return res
 
 
+def jpeg_frames(ctx, sc, reps: int = 20, quality: int = 90):
+    """JPEG compression of a rendered frame (over white, quality 90) and of a noise frame, wall clock per call."""
+    import torch
+    from paper_1611_09048_amd import device
+    vol = device.upload_volume(ctx, sc, 9)
+    img = device.new_image(sc)
+    ctx.render([device.render_job(sc, 9, img)])
+    w, h = sc.width, sc.height
+    rgba8 = torch.empty((h, w, 4), dtype=torch.uint8, device="cuda")
+    ctx.encode_rgba8(img.data_ptr(), w, h, rgba8.data_ptr(), (1.0, 1.0, 1.0))
+    noise = torch.randint(0, 256, (h, w, 4), dtype=torch.uint8, device="cuda")
+    res = dict(quality=quality)
+    for name, t in (("frame", rgba8), ("noise", noise)):
+        b = ctx.encode_jpeg(t.data_ptr(), w, h, quality)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.encode_jpeg(t.data_ptr(), w, h, quality)
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[name] = dict(ms_per_frame=round(ms, 3), bytes=len(b), bits_per_pixel=round(8 * len(b) / (w * h), 3),
+                         mpixel_per_s=round(w * h / (ms * 1e3), 1))
+    log(f"bench: jpeg {res}")
+    del vol
+    return res
+
+
 def insitu_run(ctx, n: int, width: int, height: int, steps: int = 40):
     """A field simulation on the same stream, rendered every n-th step (zero-copy sources)."""
     import torch
@@ -377,6 +402,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--jpeg-only", action="store_true",
+                    help="only compress the view-0 frame and a noise frame to JPEG (for profiling); prints that result")
     ap.add_argument("--shape", default="", help="wave_w,waves_x,unroll,lanes,min_waves instead of the tuned shape")
     args = ap.parse_args()
     if args.shape:
@@ -398,6 +425,10 @@ def main():
         log("bench: copy probe", copy_probe(ctx))
     log(f"bench: generating pic3 {args.n}^3 {args.dtype} {args.width}x{args.height}")
     sc = configs.pic3(n=args.n, width=args.width, height=args.height, dtype=args.dtype)
+    if args.jpeg_only:
+        print(json.dumps(dict(jpeg=jpeg_frames(ctx, sc, reps=args.steps))), flush=True)
+        ctx.close()
+        return
     fr = frames(ctx, sc, args.steps, args.warmup)
     # the ray-casting kernel issues FP32 vector arithmetic most of its time: an ALU
     # roofline with the method's FLOPs per scan point (FMA = 2) over the samples
@@ -439,6 +470,7 @@ def main():
                               fps=round(max(26, args.steps // 2) / f2["elapsed"], 2), tile_shape=list(f2["shape"]))
         extras["iso"] = iso_frames(ctx, args.n, args.width, args.height)
         extras["encode_rgba8"] = encode(ctx, args.width, args.height)
+        extras["jpeg"] = jpeg_frames(ctx, sc)
         extras["insitu"] = insitu_run(ctx, 128, args.width, args.height)
         extras["batch64"] = batch64(ctx, 10)
         extras["serving"] = serving(ctx, args.serve_seconds, 200.0)

@@ -223,17 +223,19 @@ class Context:
         self._check(self.lib.isaac_encode_rgba8(self.h, rgba_ptr, width, height, bg, out_ptr, flags))
 
     def _jpeg_call(self, call, width: int, height: int) -> bytes:
-        # a first guess of the stream size; on a too small buffer the library reports the size it needs
+        # a reused host buffer; on a too small one the library reports the size it needs
         size = ctypes.c_size_t(0)
-        cap = width * height * 4 + 4096
+        need = width * height * 4 + 4096
         for _ in range(2):
-            buf = ctypes.create_string_buffer(cap)
-            rc = call(buf, cap, size)
+            buf = getattr(self, "_jpeg_buf", None)
+            if buf is None or len(buf) < need:
+                self._jpeg_buf = buf = (ctypes.c_char * need)()
+            rc = call(buf, len(buf), size)
             if rc == 0:
-                return buf.raw[: size.value]
-            if rc != -1 or size.value <= cap:
+                return ctypes.string_at(buf, size.value)
+            if rc != -1 or size.value <= len(buf):
                 break
-            cap = size.value
+            need = size.value
         self._check(rc)
         raise IsaacError(rc, "jpeg encode failed")
 

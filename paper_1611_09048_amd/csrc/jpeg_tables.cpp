@@ -67,13 +67,21 @@ void jpeg_code_lengths(const uint32_t* freq256, uint8_t* len256) {
     int size[N], chain[N];
     for (int v = 0; v < 256; ++v) f[v] = freq256[v];
     f[256] = 1;
-    for (int v = 0; v < N; ++v) size[v] = 0, chain[v] = -1;
+    int live[N], n_live = 0;                   // entries with a nonzero count, ascending
+    for (int v = 0; v < N; ++v) {
+        size[v] = 0, chain[v] = -1;
+        if (f[v]) live[n_live++] = v;
+    }
     for (;;) {
         int a = -1, b = -1;
-        for (int v = 0; v < N; ++v)
+        for (int i = 0; i < n_live; ++i) {
+            const int v = live[i];
             if (f[v] && (a < 0 || f[v] <= f[a])) a = v;
-        for (int v = 0; v < N; ++v)
+        }
+        for (int i = 0; i < n_live; ++i) {
+            const int v = live[i];
             if (v != a && f[v] && (b < 0 || f[v] <= f[b])) b = v;
+        }
         if (b < 0) break;
         f[a] += f[b];
         f[b] = 0;
