@@ -689,8 +689,8 @@ __device__ __forceinline__ void march_seq(const DevJob& J, const float4* __restr
     count = n;
 }
 
-// Value of the lane D below inside a row of 16 lanes (DPP row_shr:D); lanes
-// whose source would lie in another row are never combined.
+// Value of the lane D below inside a row of 16 lanes (DPP row_shr:D); a lane
+// whose source would lie in another row reads 0.
 template <int D>
 __device__ __forceinline__ float lane_up(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x110 + D, 0xF, 0xF,
@@ -726,7 +726,9 @@ __device__ __forceinline__ void group_scan(int lane, float& c0, float& c1, float
         } else {
             o0 = lane_up<8>(c0); o1 = lane_up<8>(c1); o2 = lane_up<8>(c2); oa = lane_up<8>(a);
         }
-        if ((g & 15) >= d) {
+        // with whole rows per group the shifted-in value of a row's first lanes
+        // is 0 (bound_ctrl), the identity of the operator: no mask needed
+        if (G >= 16 || (g & 15) >= d) {
             const float t = 1.f - oa;
             c0 = fmaf(t, c0, o0);
             c1 = fmaf(t, c1, o1);
