@@ -223,9 +223,10 @@ class Context:
         self._check(self.lib.isaac_encode_rgba8(self.h, rgba_ptr, width, height, bg, out_ptr, flags))
 
     def _jpeg_call(self, call, width: int, height: int) -> bytes:
-        # a reused host buffer; on a too small one the library reports the size it needs
+        # a reused host buffer (first guess at most 16 MiB); on a too small one the
+        # library reports the size it needs and the call is repeated once
         size = ctypes.c_size_t(0)
-        need = width * height * 4 + 4096
+        need = min(width * height * 4 + 4096, 16 << 20)
         for _ in range(2):
             buf = getattr(self, "_jpeg_buf", None)
             if buf is None or len(buf) < need:

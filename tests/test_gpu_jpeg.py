@@ -102,6 +102,10 @@ def test_served_image_as_jpeg(ctx):
         got = ctx.read_image_jpeg(t, sc.width, sc.height, q, bg)
         check(got, jpeg.encode(oracle.encode_rgba8(f32, bg), q), f"served jpeg bg={bg} q{q}")
     ctx.release(t)
+    from paper_1611_09048_amd import binding
+    with pytest.raises(binding.IsaacError) as e:
+        ctx.read_image_jpeg(t, sc.width, sc.height, 90)
+    assert e.value.code == -6                     # released: unknown ticket
     del vol
 
 
