@@ -250,7 +250,9 @@ isaac_status isaac_encode_rgba8(isaac_context* ctx, const float* rgba, int width
  * also when capacity is too small (then ISAAC_ERR_INVALID_ARGUMENT and out is
  * not written).  The stream is a fixed function of (pixels, quality).  Runs on
  * the context stream (ordered after earlier work there) and returns when the
- * stream is in out; scratch memory is kept by the context between calls. */
+ * stream is in out.  Device scratch, sized for the largest stream the frame
+ * can give (about 42 bytes per pixel), is kept by the context between calls
+ * and grows with the frame size; device errors are ISAAC_ERR_DEVICE. */
 isaac_status isaac_encode_jpeg(isaac_context* ctx, const unsigned char* rgba8, int width, int height, int quality,
                                unsigned char* out, size_t capacity, size_t* out_size);
 
