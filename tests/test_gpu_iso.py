@@ -128,3 +128,24 @@ def test_iso_rejects_bricks(ctx):
     with pytest.raises(binding.IsaacError):
         ctx.render([device.render_job(sc, 7, img, mode=2)])
     del vol
+
+
+def test_iso_full_size_sampled(ctx):
+    """The iso-surface form of the 256^3 1080p benchmark scene (density surface at 1.0, |E| at
+    0.2, B without a surface) in its launch configuration; sampled pixels, hit pixels included."""
+    from parity import pixel_list
+    sc = configs.pic3()
+    sc = sc.with_(mode="iso", sources=[dataclasses.replace(s, iso=v) for s, v in
+                                       zip(sc.sources, (1.0, 0.2, float("nan")))])
+    img, cnt = render(ctx, sc)
+    img = img.reshape(sc.height, sc.width, 4)
+    cnt = cnt.reshape(sc.height, sc.width)
+    rng = np.random.default_rng(5)
+    px = pixel_list(sc.height, sc.width, 1000, rng, extra_rows=(540,), extra_cols=(960,),
+                    hit_mask=img[..., 3] > 0, n_hit=2000)
+    rec = oracle.render_pixels(sc, px)
+    st = compare(img[px[:, 1], px[:, 0]], cnt[px[:, 1], px[:, 0]], rec, label="iso pic3 256^3 1080p sampled")
+    hits = rec["rgba"][:, 3] == 1.0
+    assert hits.sum() > 500, "the sample should contain surface pixels"
+    assert st["flagged_pixels"] < 0.2 * hits.size
+    assert np.all((img[..., 3] == 0.0) | (img[..., 3] == 1.0))
