@@ -117,6 +117,25 @@ __device__ inline unsigned lane_bits(const LaneSym& s, const uint32_t* C) {
     return (unsigned)s.zrl * (t[0xF0] >> 16) + (t[s.sym] >> 16) + (unsigned)s.size;
 }
 
+// Inclusive prefix sum over the 64 lanes by DPP: a scan inside each row of 16
+// lanes (row_shr 1, 2, 4, 8; lanes whose source lies in another row add 0),
+// then the last lane of row 0 (and row 2) added into row 1 (and row 3), then
+// lane 31 into rows 2 and 3.
+template <int CTRL, int ROWS>
+__device__ inline unsigned dpp_add(unsigned v) {
+    return v + (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, true);
+}
+
+__device__ inline unsigned wave_incl_scan_dpp(unsigned v) {
+    v = dpp_add<0x111, 0xF>(v);
+    v = dpp_add<0x112, 0xF>(v);
+    v = dpp_add<0x114, 0xF>(v);
+    v = dpp_add<0x118, 0xF>(v);
+    v = dpp_add<0x142, 0xA>(v);            // row_bcast:15
+    v = dpp_add<0x143, 0xC>(v);            // row_bcast:31
+    return v;
+}
+
 __device__ inline unsigned long long wave_incl_scan64(unsigned long long v, int lane) {
     for (int o = 1; o < 64; o <<= 1) {
         const unsigned long long t = __shfl_up(v, o);
@@ -154,8 +173,8 @@ __global__ __launch_bounds__(kThreads) void jpeg_coef_kernel(const uint8_t* __re
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int r = lane >> 3, c = lane & 7;
     const int m0 = (blockIdx.x * kWaves + wave) * kMcuPerWave;
-    static_assert(sizeof(JpegTables) == 4 * kThreads, "one table word per thread");
-    reinterpret_cast<int32_t*>(&TB)[threadIdx.x] = reinterpret_cast<const int32_t*>(tab)[threadIdx.x];
+    for (int i = threadIdx.x; i < (int)(sizeof(JpegTables) / 4); i += kThreads)
+        reinterpret_cast<int32_t*>(&TB)[i] = reinterpret_cast<const int32_t*>(tab)[i];
     // this lane's pixel of each of the wave's MCUs, all loads in flight together
     // (an MCU beyond the frame reads the last one's pixel and is not stored)
     uint32_t px[kMcuPerWave];
@@ -170,6 +189,7 @@ __global__ __launch_bounds__(kThreads) void jpeg_coef_kernel(const uint8_t* __re
     int mu[8], mv[8];
     for (int i = 0; i < 8; ++i) mu[i] = TB.dct[c * 8 + i], mv[i] = TB.dct[r * 8 + i];
     const int q0 = TB.quant[0][lane], q1 = TB.quant[1][lane], zz = TB.zz[lane];
+    const unsigned r0 = TB.qinv[0][lane], r1 = TB.qinv[1][lane];
     for (int i = 0; i < kMcuPerWave; ++i) {
         const int mcu = m0 + i;
         const bool live = mcu < n_mcu;
@@ -195,8 +215,11 @@ __global__ __launch_bounds__(kThreads) void jpeg_coef_kernel(const uint8_t* __re
                 int acc = 0;
                 for (int y = 0; y < 8; ++y) acc += __mul24(mv[y], T[wave][k][y * 8 + c]);   // |T| < 2^12
                 const int f = (acc + 8192) >> 14;
+                // |f| <= 1024 for 8-bit samples, so the dividend stays below 2^12 and the
+                // reciprocal product below 2^32 (24-bit operands)
                 const int q = k ? q1 : q0;
-                const int mag = ((f < 0 ? -f : f) + (q >> 1)) / q;
+                const unsigned a = (unsigned)((f < 0 ? -f : f) + (q >> 1));
+                const int mag = (int)(__umul24(a, k ? r1 : r0) >> 20);
                 coef[((size_t)mcu * 3 + k) * 64 + zz] = (int16_t)(f < 0 ? -mag : mag);
             }
     }
@@ -270,8 +293,8 @@ __global__ __launch_bounds__(kThreads) void jpeg_bits_kernel(const int16_t* __re
             nb[i] = (unsigned)s.zrl * t[0xF0] + t[s.sym] + (unsigned)s.size;
         }
     }
-    for (int o = 32; o > 0; o >>= 1)
-        for (int i = 0; i < kBlocksPerWave; ++i) nb[i] += __shfl_xor(nb[i], o);
+    for (int i = 0; i < kBlocksPerWave; ++i)
+        nb[i] = (unsigned)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(nb[i]), 63);
     unsigned wave_total = 0;
     for (int i = 0; i < kBlocksPerWave; ++i) {
         if (b0 + i >= n_blocks) break;
@@ -361,11 +384,7 @@ __global__ __launch_bounds__(kThreads) void jpeg_pack_kernel(const int16_t* __re
     }
     unsigned nb[kBlocksPerWave];
     for (int i = 0; i < kBlocksPerWave; ++i) nb[i] = ex[i];
-    for (int o = 1; o < 64; o <<= 1)
-        for (int i = 0; i < kBlocksPerWave; ++i) {
-            const unsigned t = __shfl_up(ex[i], o);
-            if (lane >= o) ex[i] += t;
-        }
+    for (int i = 0; i < kBlocksPerWave; ++i) ex[i] = wave_incl_scan_dpp(ex[i]);
     for (int i = 0; i < kBlocksPerWave; ++i) {
         const LaneSym& s = sy[i];
         int q = start + (int)(ex[i] - nb[i]);

@@ -16,6 +16,7 @@ namespace isaac {
 struct JpegTables {
     int32_t dct[64];        // M[u][x] = C(u)/2 cos((2x+1) u pi/16), 12 fractional bits, row u
     int32_t quant[2][64];   // luma, chroma divisors, natural (row-major v, u) order
+    int32_t qinv[2][64];    // ceil(2^20 / quant): floor(a / q) = (a * qinv) >> 20 for 0 <= a < 4096
     int32_t zz[64];         // natural index v*8+u -> zigzag position
 };
 

@@ -49,6 +49,7 @@ void jpeg_fill_tables(int quality, JpegTables* t) {
     for (int i = 0; i < 64; ++i) {
         t->quant[0][i] = std::min(255, std::max(1, (kLuma[i] * scale + 50) / 100));
         t->quant[1][i] = std::min(255, std::max(1, (kChroma[i] * scale + 50) / 100));
+        for (int c = 0; c < 2; ++c) t->qinv[c][i] = ((1 << 20) + t->quant[c][i] - 1) / t->quant[c][i];
     }
     const double pi = 3.14159265358979323846;
     for (int u = 0; u < 8; ++u)
