@@ -26,10 +26,11 @@ SHIM = r"""
 extern "C" {
 void shim_lengths(const uint32_t* f, uint8_t* l) { isaac::jpeg_code_lengths(f, l); }
 int shim_canonical(const uint8_t* l, uint32_t* p, uint8_t* b, uint8_t* v) { return isaac::jpeg_canonical(l, p, b, v); }
-void shim_tables(int q, int32_t* dct, int32_t* quant, int32_t* zz) {
+void shim_tables(int q, int32_t* dct, int32_t* quant, int32_t* zz, int32_t* qinv) {
     isaac::JpegTables t;
     isaac::jpeg_fill_tables(q, &t);
     for (int i = 0; i < 64; ++i) dct[i] = t.dct[i], zz[i] = t.zz[i], quant[i] = t.quant[0][i], quant[64 + i] = t.quant[1][i];
+    for (int i = 0; i < 64; ++i) qinv[i] = t.qinv[0][i], qinv[64 + i] = t.qinv[1][i];
 }
 size_t shim_headers(int w, int h, int q, const uint8_t* bits, const uint8_t* vals, const int* nvals, uint8_t* out) {
     isaac::JpegTables t;
@@ -118,7 +119,8 @@ def test_tables_match_oracle(lib, quality):
     dct = (ctypes.c_int32 * 64)()
     quant = (ctypes.c_int32 * 128)()
     zz = (ctypes.c_int32 * 64)()
-    lib.shim_tables(quality, dct, quant, zz)
+    qinv = (ctypes.c_int32 * 128)()
+    lib.shim_tables(quality, dct, quant, zz, qinv)
     assert np.array_equal(np.array(dct).reshape(8, 8), jpeg.dct_matrix())
     qt = jpeg.scaled_tables(quality)
     assert np.array_equal(np.array(quant[:64]).reshape(8, 8), qt[0])
@@ -126,6 +128,12 @@ def test_tables_match_oracle(lib, quality):
     order = jpeg.zigzag_order()
     for k, (r, c) in enumerate(order):
         assert zz[r * 8 + c] == k
+    # the device quantises by reciprocal multiply: exact for every dividend below 2^12
+    # (|f| <= 1024 plus half a divisor), with 24-bit operands and a product below 2^32
+    a = np.arange(4096, dtype=np.uint64)
+    for q, r in zip(quant, qinv):
+        assert 0 < r < (1 << 24) and int(a[-1]) * r < (1 << 32)
+        assert np.array_equal((a * np.uint64(r)) >> np.uint64(20), a // np.uint64(q))
 
 
 @pytest.mark.parametrize("shape,quality", [((1, 1), 100), ((37, 53), 90), ((8, 16), 20)])
