@@ -61,39 +61,44 @@ void jpeg_fill_tables(int quality, JpegTables* t) {
 
 void jpeg_code_lengths(const uint32_t* freq256, uint8_t* len256) {
     // Annex K.2: repeatedly merge the two least frequent entries (ties to the
-    // larger symbol value), counting how often each symbol's subtree is
-    // merged; entry 256 has count 1 and reserves the all-ones code.
+    // larger symbol value; the merged entry keeps the first one's value), a
+    // symbol's code size being the number of merges its subtree takes part in;
+    // entry 256 has count 1 and reserves the all-ones code.  The two least
+    // entries come from a heap ordered by (count, -value), so a frame's tables
+    // take O(n log n) instead of a scan of all entries per merge.
     constexpr int N = 257;
-    uint64_t f[N];
-    int size[N], chain[N];
-    for (int v = 0; v < 256; ++v) f[v] = freq256[v];
-    f[256] = 1;
-    int live[N], n_live = 0;                   // entries with a nonzero count, ascending
+    struct Entry {
+        uint64_t f;
+        int v, node;
+    };
+    auto later = [](const Entry& a, const Entry& b) { return a.f != b.f ? a.f > b.f : a.v < b.v; };
+    Entry heap[N];
+    int n_heap = 0;
+    int parent[2 * N];
     for (int v = 0; v < N; ++v) {
-        size[v] = 0, chain[v] = -1;
-        if (f[v]) live[n_live++] = v;
+        const uint64_t f = v < 256 ? freq256[v] : 1;
+        parent[v] = -1;
+        if (f) heap[n_heap++] = Entry{f, v, v};
     }
-    for (;;) {
-        int a = -1, b = -1;
-        for (int i = 0; i < n_live; ++i) {
-            const int v = live[i];
-            if (f[v] && (a < 0 || f[v] <= f[a])) a = v;
-        }
-        for (int i = 0; i < n_live; ++i) {
-            const int v = live[i];
-            if (v != a && f[v] && (b < 0 || f[v] <= f[b])) b = v;
-        }
-        if (b < 0) break;
-        f[a] += f[b];
-        f[b] = 0;
-        for (int v = a;; v = chain[v]) {       // deepen a's subtree, then hang b's behind it
-            ++size[v];
-            if (chain[v] < 0) {
-                chain[v] = b;
-                break;
-            }
-        }
-        for (int v = b; v >= 0; v = chain[v]) ++size[v];
+    std::make_heap(heap, heap + n_heap, later);
+    int next_node = N;
+    while (n_heap > 1) {
+        std::pop_heap(heap, heap + n_heap, later);
+        const Entry a = heap[--n_heap];
+        std::pop_heap(heap, heap + n_heap, later);
+        const Entry b = heap[--n_heap];
+        const int p = next_node++;
+        parent[p] = -1;
+        parent[a.node] = p;
+        parent[b.node] = p;
+        heap[n_heap++] = Entry{a.f + b.f, a.v, p};
+        std::push_heap(heap, heap + n_heap, later);
+    }
+    int size[N];
+    for (int v = 0; v < N; ++v) {
+        int d = 0;
+        for (int q = parent[v]; q >= 0; q = parent[q]) ++d;
+        size[v] = d;
     }
     int count[N + 1] = {0};
     int deepest = 0;
@@ -113,11 +118,16 @@ void jpeg_code_lengths(const uint32_t* freq256, uint8_t* len256) {
     int longest = 16;
     while (count[longest] == 0) --longest;
     --count[longest];                          // the reserved entry's code
-    // lengths back to the symbols in order of (merge depth, value)
-    int order[256], n = 0;
+    // lengths back to the symbols in order of (merge depth, value): a counting sort by depth
+    int per_depth[N + 1] = {0};
     for (int v = 0; v < 256; ++v)
-        if (size[v]) order[n++] = v;
-    std::stable_sort(order, order + n, [&](int x, int y) { return size[x] < size[y]; });
+        if (size[v]) ++per_depth[size[v]];
+    int first[N + 1];
+    first[0] = 0;
+    for (int d = 1; d <= N; ++d) first[d] = first[d - 1] + per_depth[d - 1];
+    int order[256];
+    for (int v = 0; v < 256; ++v)
+        if (size[v]) order[first[size[v]]++] = v;
     memset(len256, 0, 256);
     int k = 0;
     for (int l = 1; l <= 16; ++l)
@@ -125,13 +135,16 @@ void jpeg_code_lengths(const uint32_t* freq256, uint8_t* len256) {
 }
 
 int jpeg_canonical(const uint8_t* len256, uint32_t* packed256, uint8_t* bits16, uint8_t* vals256) {
-    int n = 0;
-    for (int l = 1; l <= 16; ++l) {
-        int c = 0;
-        for (int v = 0; v < 256; ++v)
-            if (len256[v] == l) vals256[n++] = (uint8_t)v, ++c;
-        bits16[l - 1] = (uint8_t)c;
-    }
+    // symbols by (length, value): a counting sort by length
+    int per_len[17] = {0};
+    for (int v = 0; v < 256; ++v) ++per_len[len256[v]];
+    int first[17];
+    first[1] = 0;
+    for (int l = 2; l <= 16; ++l) first[l] = first[l - 1] + per_len[l - 1];
+    const int n = first[16] + per_len[16];
+    for (int l = 1; l <= 16; ++l) bits16[l - 1] = (uint8_t)per_len[l];
+    for (int v = 0; v < 256; ++v)
+        if (len256[v]) vals256[first[len256[v]]++] = (uint8_t)v;
     memset(packed256, 0, 256 * sizeof(uint32_t));
     uint32_t code = 0;
     int l = n ? len256[vals256[0]] : 0;
