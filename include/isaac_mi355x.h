@@ -216,6 +216,20 @@ isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int
 isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const float* const* depth, int n_layers,
                              int width, int height, float* out, unsigned flags);
 
+/* Freeze a volume whose sources will not change until it is redefined (a
+ * resident data set explored by many renders or served requests): every
+ * source's functor chain is evaluated once per voxel now (guards included),
+ * into the library-owned derived volume of 4 bytes per voxel and source, and
+ * every later render or served request of the volume, whatever its clip
+ * planes and enabled sources, reads those values instead of the sources.
+ * Images are the same bit for bit.  The sources must be persistent and at
+ * most 4; their update callbacks are called once here and still before each
+ * render.  The caller must not change the sources' memory while the volume is
+ * frozen; isaac_set_sources (redefinition) thaws it.  A volume whose sources
+ * are read directly anyway (plain packed FP32 scalars) stays as it is.
+ * Synchronous: returns when the derived values are complete. */
+isaac_status isaac_freeze_volume(isaac_context* ctx, int volume_id);
+
 /* Frame encode (the step after compositing, where the root rank compresses
  * the image before sending it, Sec. 3.4): each pixel of a premultiplied
  * RGBA32F image (device, width*height*4 floats) is quantized to 8 bits per

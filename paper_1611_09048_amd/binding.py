@@ -73,7 +73,7 @@ class RenderDesc(ctypes.Structure):
 EXPORTS = ["isaac_init", "isaac_destroy", "isaac_last_error", "isaac_init_error", "isaac_set_sources",
            "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_composite", "isaac_encode_rgba8",
            "isaac_timing", "isaac_set_tile_shape", "isaac_get_tile_shape", "isaac_submit", "isaac_submit_batch",
-           "isaac_poll", "isaac_release", "isaac_read_image", "isaac_read_image_rgba8", "isaac_encode_jpeg", "isaac_read_image_jpeg", "isaac_serving_usage",
+           "isaac_poll", "isaac_release", "isaac_read_image", "isaac_read_image_rgba8", "isaac_encode_jpeg", "isaac_read_image_jpeg", "isaac_freeze_volume", "isaac_serving_usage",
            "isaac_check_functor_chain", "isaac_version"]
 
 _lib = None
@@ -109,6 +109,7 @@ def load(path: Optional[str] = None):
     lib.isaac_encode_rgba8.argtypes = [c_ctx, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_uint]
     lib.isaac_read_image_rgba8.argtypes = [c_ctx, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
+    lib.isaac_freeze_volume.argtypes = [c_ctx, ctypes.c_int]
     lib.isaac_encode_jpeg.argtypes = [c_ctx, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     lib.isaac_read_image_jpeg.argtypes = [c_ctx, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
@@ -221,6 +222,10 @@ class Context:
         """Quantize a device RGBA32F image to device RGBA8 (optionally over an opaque rgb background)."""
         bg = (ctypes.c_float * 3)(*map(float, background)) if background is not None else None
         self._check(self.lib.isaac_encode_rgba8(self.h, rgba_ptr, width, height, bg, out_ptr, flags))
+
+    def freeze_volume(self, volume_id: int):
+        """Evaluate the volume's chains once per voxel; later renders read those values (sources must not change)."""
+        self._check(self.lib.isaac_freeze_volume(self.h, volume_id))
 
     def _jpeg_call(self, call, width: int, height: int) -> bytes:
         # a reused host buffer (first guess at most 16 MiB); on a too small one the

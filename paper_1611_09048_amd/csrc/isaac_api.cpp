@@ -215,6 +215,11 @@ struct Volume {
     // derived volume (chain outputs per voxel), rebuilt by each render call that uses it
     void* derived = nullptr;
     size_t derived_bytes = 0;
+    // frozen (isaac_freeze_volume): the derived volume holds every source's
+    // values and stays valid until the sources are redefined; frozen_src[s] is
+    // how source s is read from it
+    bool frozen = false;
+    DevSource frozen_src[kMaxSources];
 };
 
 struct TfSlot {
@@ -967,6 +972,7 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
         if (std::find(vols.begin(), vols.end(), jobs[i].volume_id) == vols.end()) vols.push_back(jobs[i].volume_id);
     for (int vid : vols) {
         Volume& v = ctx->volumes[vid];
+        if (v.frozen) continue;       // its jobs already read the frozen derived volume
         int comp_of[kMaxSources];
         for (int s = 0; s < kMaxSources; ++s) comp_of[s] = -1;
         double est = 0.0;
@@ -1117,6 +1123,25 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
                 ds.packed = 1;
             }
         }
+    }
+    // frozen volumes: every job reads the derived values (render and serving calls alike)
+    for (int i = 0; i < n; ++i) {
+        const Volume& v = ctx->volumes[jobs[i].volume_id];
+        if (!v.frozen || (flags & ISAAC_DIRECT)) continue;
+        DevJob& dj = djs[i];
+        for (int k = 0; k < dj.n_src; ++k) {
+            const DevSource& f = v.frozen_src[dj.src_index[k]];
+            DevSource& d = dj.src[k];
+            std::memcpy(d.base, f.base, sizeof d.base);
+            std::memcpy(d.num_records, f.num_records, sizeof d.num_records);
+            std::memcpy(d.comp_off, f.comp_off, sizeof d.comp_off);
+            std::memcpy(d.stride, f.stride, sizeof d.stride);
+            d.packed = f.packed;
+            d.f_dim = 1;
+            d.dtype = DT_F32;
+            d.n_ops = 0;
+        }
+        if (dj.mode != ISAAC_ISO) dj.sig = signature_of(dj);
     }
     if (allow_derive && !(flags & ISAAC_DIRECT)) {
         st = derive_volumes(ctx, jobs, djs, (flags & ISAAC_DERIVE) != 0, stream);
@@ -1367,6 +1392,7 @@ isaac_status isaac_set_sources(isaac_context* ctx, int volume_id, const int32_t 
         v.derived = nullptr;
         v.derived_bytes = 0;
     }
+    v.frozen = false;
     std::vector<int32_t> tf(n_src, 0);
     for (int s = 0; s < n_src && s < (int)v.tf.size(); ++s) tf[s] = v.tf[s];
     v.defined = true;
@@ -1439,6 +1465,57 @@ isaac_status isaac_encode_rgba8(isaac_context* ctx, const float* rgba, int width
     int rc = launch_encode_rgba8(rgba, (int64_t)width * height, background, out, ctx->stream);
     if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "encode launch: %s", hipGetErrorString((hipError_t)rc));
     if (!(flags & ISAAC_ASYNC)) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return ISAAC_OK;
+}
+
+isaac_status isaac_freeze_volume(isaac_context* ctx, int volume_id) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (volume_id < 0 || volume_id >= (int)ctx->volumes.size() || !ctx->volumes[volume_id].defined)
+        return set_err(ctx, ISAAC_ERR_NOT_FOUND, "volume %d is not defined", volume_id);
+    Volume& v = ctx->volumes[volume_id];
+    if (v.frozen) return ISAAC_OK;
+    const int ns = (int)v.src.size();
+    if (ns < 1 || ns > kMaxDerived)
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "a frozen volume has 1..%d sources", kMaxDerived);
+    for (int s = 0; s < ns; ++s) {
+        if (!v.src[s].desc.persistent)
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source %d is not persistent: it cannot be frozen", s);
+        if (!v.src[s].desc.comp[0]) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "source %d has no data", s);
+    }
+    // a job that reads every source: one pixel, orthographic, no clip planes
+    isaac_render_desc d;
+    std::memset(&d, 0, sizeof d);
+    d.volume_id = volume_id;
+    d.width = d.height = 1;
+    d.projection = ISAAC_ORTHOGRAPHIC;
+    for (int a = 0; a < 3; ++a) d.center[a] = 0.5 * v.dims[a];
+    d.eye[0] = d.center[0] - v.dims[0] - 1.0;
+    d.eye[1] = d.center[1];
+    d.eye[2] = d.center[2];
+    d.up[2] = 1.0;
+    d.ortho_height = 1.0;
+    d.step = 1.0;
+    d.interpolation = ISAAC_TRILINEAR;
+    int32_t en[kMaxSources];
+    float w[kMaxSources];
+    for (int s = 0; s < ns; ++s) en[s] = 1, w[s] = 1.0f;
+    d.enabled = en;
+    d.weights = w;
+    std::vector<DevJob> djs(1);
+    int na = 0;
+    st = build_job(ctx, d, false, djs[0], &na);
+    if (st) return st;
+    st = prepare_sources(ctx, &d, 1);
+    if (st) return st;
+    st = derive_volumes(ctx, &d, djs, true, ctx->stream);
+    if (st) return st;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const DevJob& dj = djs[0];
+    if (dj.n_src != ns || !v.derived || dj.src[0].base[0] != reinterpret_cast<uint64_t>(v.derived))
+        return ISAAC_OK;   // the sources are read directly already (plain FP32 scalars) or no memory: nothing to freeze
+    for (int k = 0; k < dj.n_src; ++k) v.frozen_src[dj.src_index[k]] = dj.src[k];
+    v.frozen = true;
     return ISAAC_OK;
 }
 

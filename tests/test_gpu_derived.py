@@ -130,3 +130,68 @@ def test_derived_skips_clipped_voxels_only(ctx):
                      sources=[dataclasses.replace(s, iso=v) for s, v in zip(base.sources, (1.0, 0.2, float("nan")))])
     a, b = both(ctx, iso, vid=8)
     assert_same(a, b, "heavy clip iso")
+
+
+def render_into(ctx, sc, vid, flags=0, **overrides):
+    import torch
+    from paper_1611_09048_amd import device
+    img, cnt = device.new_image(sc), device.new_counts(sc)
+    ctx.render([device.render_job(sc, vid, img, cnt, **overrides)], flags)
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), cnt.cpu().numpy()
+
+
+def test_frozen_volume_equals_direct(ctx):
+    """isaac_freeze_volume: one derive of every source, then renders with other clip planes,
+    a source disabled, the iso mode and served requests all equal the direct renders."""
+    import torch
+    from paper_1611_09048_amd import DIRECT, device
+    sc = configs.pic3(n=40, width=128, height=96, direction=(0.5, -0.4, 0.7))
+    vol = device.upload_volume(ctx, sc, 11)
+    ctx.freeze_volume(11)
+    ctx.freeze_volume(11)                               # already frozen: no-op
+    cases = [("as scene", sc, {}),
+             ("no clip", sc.with_(clip=[]), {}),
+             ("other view", sc.with_(camera=configs.orbit_camera(sc.dims, (-0.3, 0.8, -0.5))), {}),
+             ("source 1 off", sc, dict(enabled=[1, 0, 1])),
+             ("nearest", sc.with_(interpolation=0), {})]
+    for label, s, kw in cases:
+        a = render_into(ctx, s, 11, DIRECT, **kw)
+        b = render_into(ctx, s, 11, 0, **kw)
+        assert_same(a, b, f"frozen {label}")
+    iso = sc.with_(mode="iso", sources=[dataclasses.replace(x, iso=v) for x, v in
+                                        zip(sc.sources, (1.0, 0.2, float("nan")))])
+    assert_same(render_into(ctx, iso, 11, DIRECT), render_into(ctx, iso, 11, 0), "frozen iso")
+    # a served request reads the frozen values too
+    t = ctx.submit(device.render_job(sc, 11, device.new_image(sc)))
+    served = ctx.read_image(t, np.zeros((sc.height, sc.width, 4), dtype=np.float32))
+    ctx.release(t)
+    direct = render_into(ctx, sc, 11, DIRECT)[0]
+    assert np.array_equal(served, direct)
+    # redefinition thaws: new data is read
+    sc2 = configs.pic3(n=40, width=128, height=96, seed=99, direction=(0.5, -0.4, 0.7))
+    vol2 = device.upload_volume(ctx, sc2, 11)
+    assert_same(render_into(ctx, sc2, 11, DIRECT), render_into(ctx, sc2, 11, 0), "thawed after redefinition")
+    img, cnt = render_into(ctx, sc2, 11, 0)
+    compare(img.reshape(-1, 4), cnt.reshape(-1), oracle.render(sc2, threads=8), label="thawed vs oracle")
+    del vol, vol2
+    torch.cuda.synchronize()
+
+
+def test_freeze_rejections_and_plain_volume(ctx):
+    from paper_1611_09048_amd import DIRECT, binding, device
+    with pytest.raises(binding.IsaacError) as e:
+        ctx.freeze_volume(200)                          # never defined
+    assert e.value.code == -6
+    base = configs.pic3(n=24, width=48, height=40)
+    s0, s1, s2 = base.sources
+    sc = base.with_(sources=[s0, s1, dataclasses.replace(s2, persistent=False)])
+    vol = device.upload_volume(ctx, sc, 12)
+    with pytest.raises(binding.IsaacError) as e:
+        ctx.freeze_volume(12)
+    assert e.value.code == -1
+    plain = configs.plain_scalar(n=32, width=64, height=48)
+    vol2 = device.upload_volume(ctx, plain, 13)
+    ctx.freeze_volume(13)                               # plain FP32 scalar: read directly, nothing to freeze
+    assert_same(render_into(ctx, plain, 13, DIRECT), render_into(ctx, plain, 13, 0), "plain frozen")
+    del vol, vol2
