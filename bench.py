@@ -249,20 +249,23 @@ def batch64(ctx, steps):
     return res
 
 
-def serving(ctx, duration: float, rate: float, n: int = 512, depth: int = 256):
-    """Continuous-batching server on a resident n x n x depth three-source volume."""
+def serving(ctx, duration: float, rate: float, n: int = 512, depth: int = 256, freeze: bool = True):
+    """Continuous-batching server on a resident n x n x depth three-source volume (frozen: its
+    chains evaluated once per voxel when it is loaded, as a server of a fixed data set would)."""
     from paper_1611_09048_amd import device, serve
     from scenes import configs
     dims = (n, n, depth)
     vol_scene = configs.pic3(dims=dims, width=16, height=16)
     vol = device.upload_volume(ctx, vol_scene, 200)
+    if freeze:
+        ctx.freeze_volume(200)
     ex = serve.DeviceExecutor(ctx, vol, dims)
     srv = serve.Server(ex, time.perf_counter, max_batch=16, max_batches_in_flight=3)
     reqs = configs.serving_requests(11, dims, n_clients=4, rate_per_client=rate / 4, duration=duration,
                                     base_tfs=[s.tf for s in vol_scene.sources])
     dur = serve.run(srv, reqs, time.perf_counter, make_job=serve.job_from_request)
     out = srv.summary(dur)
-    out.update(volume=list(dims), offered_rate=rate, requests=len(reqs))
+    out.update(volume=list(dims), offered_rate=rate, requests=len(reqs), frozen=freeze)
     log(f"bench: serving {out}")
     del vol
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
@@ -475,6 +478,7 @@ def main():
         extras["batch64"] = batch64(ctx, 10)
         extras["serving"] = serving(ctx, args.serve_seconds, 200.0)
         extras["serving_stress"] = serving(ctx, max(2.0, args.serve_seconds / 2), 2000.0)
+        extras["serving_unfrozen"] = serving(ctx, max(2.0, args.serve_seconds / 2), 200.0, freeze=False)
         out["extras"] = extras
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
