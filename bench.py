@@ -414,7 +414,7 @@ def main():
         FORCED_SHAPE = tuple(int(v) for v in args.shape.split(","))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): every job of this ray caster is "
-              f"rendered by one GPU and there is no multi-GPU path in this build", file=sys.stderr)
+              f"rendered by one GPU; the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
