@@ -123,3 +123,10 @@ def test_jpeg_rejects_bad_arguments(ctx):
     buf = ctypes.create_string_buffer(8)
     rc = ctx.lib.isaac_encode_jpeg(ctx.h, a.data_ptr(), 16, 16, 50, buf, 8, ctypes.byref(size))
     assert rc == -1 and size.value == len(jpeg.encode(np.zeros((16, 16, 4), np.uint8), 50))
+
+
+@pytest.mark.parametrize("shape", [(1, 65535), (65535, 1), (9, 4097)])
+def test_jpeg_extreme_aspect(ctx, shape):
+    """The largest frame side the format allows (SOF fields 0xFFFF), one pixel across."""
+    img = frame("smooth", *shape, seed=3)
+    check(device_jpeg(ctx, img, 60), jpeg.encode(img, 60), f"jpeg {shape} q60")
