@@ -101,6 +101,19 @@ def test_pic3_full_size_sampled(ctx):
     assert np.isfinite(img).all() and img.min() >= 0.0 and img.max() <= 1.0 + 1e-6
 
 
+def test_pic3_4k_sampled(ctx):
+    """The benchmark volume at 3840x2160 (four times the pixels and tiles of 1080p); sampled pixels."""
+    sc = configs.pic3(width=3840, height=2160, direction=(0.3, 0.5, -0.8))
+    img, cnt = gpu_render(ctx, sc)
+    rng = np.random.default_rng(4)
+    px = pixel_list(sc.height, sc.width, 1000, rng, extra_rows=(1080, 2159), extra_cols=(1920, 3839),
+                    hit_mask=img[..., 3] > 0, n_hit=2000)
+    rec = oracle.render_pixels(sc, px)
+    stats = compare(img[px[:, 1], px[:, 0]], cnt[px[:, 1], px[:, 0]], rec, label="pic3 256^3 4K sampled")
+    assert stats["samples"] > 1e5
+    assert np.isfinite(img).all()
+
+
 def test_closed_form_slab_on_gpu(ctx):
     """The constant-42 source behind add(-41.5), constant TF (a=0.1): A = 1 - 0.9^16 exactly in closed form."""
     dims = (8, 6, 5)
