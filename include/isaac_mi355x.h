@@ -21,7 +21,11 @@
  *     [x,x+1]x[y,y+1]x[z,z+1]; its value sits at the cell centre; the local
  *     box is [0,Nx]x[0,Ny]x[0,Nz].
  *   Pointers: "device" pointers are HIP device addresses on the context's
- *     device; "host" pointers are ordinary process memory.
+ *     device; "host" pointers are ordinary process memory.  Device images
+ *     are accessed a pixel at a time: RGBA32F images must be 16-byte
+ *     aligned, sample counts, depths and RGBA8 images 4-byte aligned
+ *     (ISAAC_ERR_INVALID_ARGUMENT otherwise); source components must be
+ *     aligned to their element size.
  *   Ownership: the library never writes to source memory and never frees
  *     memory it did not allocate.  Strings and arrays passed in are copied
  *     before the call returns unless stated otherwise.

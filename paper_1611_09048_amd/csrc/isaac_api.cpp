@@ -320,6 +320,10 @@ isaac_status set_err(isaac_context* ctx, isaac_status code, const char* fmt, ...
     return code;
 }
 
+// Device pointers are read and written a whole element at a time: RGBA32F
+// pixels 16 bytes, counts, depths and RGBA8 pixels 4 bytes.
+inline bool aligned_to(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
 #define HIP_TRY(ctx, expr)                                                                       \
     do {                                                                                         \
         hipError_t e_ = (expr);                                                                  \
@@ -608,6 +612,9 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
     if (!(j.ert_threshold >= 0.0f) || !std::isfinite(j.ert_threshold))
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "ert_threshold must be >= 0");
     if (need_out && !j.out_rgba) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "out_rgba is NULL");
+    if (need_out && (!aligned_to(j.out_rgba, 16) || !aligned_to(j.out_samples, 4)))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "out_rgba must be 16-byte and out_samples 4-byte aligned");
+    if (!aligned_to(j.out_depth, 4)) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "out_depth must be 4-byte aligned");
     if (j.mode != ISAAC_VOLUME && j.mode != ISAAC_ISO)
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "unknown render mode %d", j.mode);
     if (j.mode == ISAAC_ISO && j.brick_origin)
@@ -1444,8 +1451,12 @@ isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const
     if (st) return st;
     if (n_layers < 1 || n_layers > kMaxLayers || !rgba || !depth || !out || width < 1 || height < 1)
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "composite needs 1..%d layers, pointers and a size", kMaxLayers);
-    for (int l = 0; l < n_layers; ++l)
+    for (int l = 0; l < n_layers; ++l) {
         if (!rgba[l] || !depth[l]) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "layer %d has a NULL pointer", l);
+        if (!aligned_to(rgba[l], 16) || !aligned_to(depth[l], 4))
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "layer %d: rgba must be 16-byte, depth 4-byte aligned", l);
+    }
+    if (!aligned_to(out, 16)) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "out must be 16-byte aligned");
     int rc = launch_composite(rgba, depth, n_layers, (int64_t)width * height, out, ctx->stream);
     if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "composite launch: %s", hipGetErrorString((hipError_t)rc));
     if (!(flags & ISAAC_ASYNC)) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1458,6 +1469,8 @@ isaac_status isaac_encode_rgba8(isaac_context* ctx, const float* rgba, int width
     if (st) return st;
     if (!rgba || !out || width < 1 || height < 1)
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "encode needs an image, an output and a size");
+    if (!aligned_to(rgba, 16) || !aligned_to(out, 4))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "rgba must be 16-byte and out 4-byte aligned");
     if (background)
         for (int c = 0; c < 3; ++c)
             if (!(background[c] >= 0.f && background[c] <= 1.f))
@@ -1523,6 +1536,7 @@ isaac_status isaac_encode_jpeg(isaac_context* ctx, const unsigned char* rgba8, i
                                unsigned char* out, size_t capacity, size_t* out_size) {
     isaac_status st = check_ctx(ctx);
     if (st) return st;
+    if (rgba8 && !aligned_to(rgba8, 4)) return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "rgba8 must be 4-byte aligned");
     if (!ctx->jpeg) ctx->jpeg = isaac::jpeg_work_create();
     char msg[256] = {0};
     const int rc = isaac::jpeg_encode(ctx->jpeg, rgba8, width, height, quality, ctx->stream, out, capacity, out_size,

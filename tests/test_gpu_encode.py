@@ -83,3 +83,28 @@ def test_encode_rejects_bad_arguments(ctx):
         ctx.encode_rgba8(a.data_ptr(), 2, 2, b.data_ptr(), (0.0, 2.0, 0.0))
     with pytest.raises(binding.IsaacError):
         ctx.encode_rgba8(a.data_ptr(), 0, 2, b.data_ptr())
+
+
+def test_misaligned_pointers_rejected(ctx):
+    """Images are accessed a pixel at a time: misaligned device pointers are refused before any launch."""
+    import torch
+    from paper_1611_09048_amd import binding, device
+    a = torch.zeros((4, 4, 4), device="cuda")
+    b = torch.zeros((4, 4, 4), dtype=torch.uint8, device="cuda")
+    for rgba, out in ((a.data_ptr() + 4, b.data_ptr()), (a.data_ptr(), b.data_ptr() + 2)):
+        with pytest.raises(binding.IsaacError) as e:
+            ctx.encode_rgba8(rgba, 2, 2, out)
+        assert e.value.code == -1
+    with pytest.raises(binding.IsaacError) as e:
+        ctx.encode_jpeg(b.data_ptr() + 1, 2, 2, 90)
+    assert e.value.code == -1
+    sc = configs.pic3(n=16, width=8, height=8)
+    vol = device.upload_volume(ctx, sc, 9)
+    img = torch.zeros((9, 8, 4), device="cuda")
+    with pytest.raises(binding.IsaacError) as e:
+        ctx.render([device.render_job(sc, 9, img, out_rgba=img.data_ptr() + 8)])
+    assert e.value.code == -1
+    with pytest.raises(binding.IsaacError) as e:
+        ctx.composite([img.data_ptr() + 4], [img.data_ptr()], 2, 2, img.data_ptr())
+    assert e.value.code == -1
+    del vol
