@@ -109,3 +109,22 @@ def test_brick_depth_and_single_layer(ctx):
     assert np.array_equal(np.isfinite(d), cnt > 0)
     assert (cnt > 0).any() and (cnt == 0).any()
     del vol
+
+
+def test_bricks_full_size(ctx):
+    """The benchmark volume (256^3, 1920x1080) cut into 8 bricks of 128^3, as 8 ranks would hold
+    it: the composite equals the whole-volume render to FP32 compositing order, and sampled
+    pixels match the oracle."""
+    from paper_1611_09048_amd import device
+    from parity import pixel_list
+    sc = configs.pic3()
+    whole, _ = device.render_scene(ctx, sc, ert_threshold=NO_TERMINATION, count=False)
+    comp, nl = render_bricks(ctx, sc, ([0, 128, 256],) * 3)
+    diff = np.abs(comp - whole).max()
+    log(f"bricks 256^3 1080p ({nl} layers): max |composite - whole| = {diff:.3e}")
+    assert nl == 8 and np.isfinite(comp).all()
+    assert diff <= 1e-5
+    rng = np.random.default_rng(8)
+    px = pixel_list(sc.height, sc.width, 500, rng, hit_mask=whole[..., 3] > 0, n_hit=1500)
+    rec = oracle.render_pixels(sc, px, ert_threshold=NO_TERMINATION)
+    compare(comp[px[:, 1], px[:, 0]], None, rec, label="8-brick composite 1080p vs oracle (sampled)")
