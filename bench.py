@@ -208,6 +208,55 @@ def frames(ctx, sc, steps, warmup, log_prefix=""):
     return out
 
 
+def bricks8(ctx, sc, reps: int = 5):
+    """One GPU's share of the sort-last design: the 256^3 volume as 8 bricks of 128^3 (one per
+    rank), each rendered on its own at 1080p on the global step grid, then the 8-layer
+    over-composite. Reports the mean brick render (ray-casting kernel) and the composite time."""
+    import torch
+    from paper_1611_09048_amd import ASYNC, TIMING, device
+    from scenes import make_source
+    half = sc.dims[0] // 2
+    vols, layers, depths, jobs = [], [], [], []
+    for k, (x, y, z) in enumerate([(x, y, z) for x in (0, half) for y in (0, half) for z in (0, half)]):
+        srcs = []
+        for s in sc.sources:
+            v = s.values[z:z + half + 2, y:y + half + 2, x:x + half + 2]    # global index i -> array i + 1
+            srcs.append(make_source(s.name, v.astype(np.float32) if s.dtype == "f32" else v, dtype=s.dtype,
+                                    guard=1, chain=s.chain, weight=s.weight, tf=s.tf))
+        bs = sc.with_(dims=(half, half, half), sources=srcs)
+        vols.append(device.upload_volume(ctx, bs, 240 + k))
+        img = device.new_image(sc)
+        dep = torch.empty((sc.height, sc.width), device="cuda")
+        layers.append(img)
+        depths.append(dep)
+        jobs.append(device.render_job(sc, 240 + k, img, brick_origin=(x, y, z), global_dims=sc.dims,
+                                      out_depth=dep.data_ptr(), ert_threshold=2.0))
+    out = device.new_image(sc)
+    for j in jobs:
+        ctx.render([j])
+    torch.cuda.synchronize()
+    ctx.timing()
+    for _ in range(reps):
+        for j in jobs:
+            ctx.render([j], ASYNC | TIMING)
+    torch.cuda.synchronize()
+    ms, n = ctx.timing()
+    lp, dp = [l.data_ptr() for l in layers], [d.data_ptr() for d in depths]
+    ctx.composite(lp, dp, sc.width, sc.height, out.data_ptr())
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    a.record(stream)
+    for _ in range(reps):
+        ctx.composite(lp, dp, sc.width, sc.height, out.data_ptr(), 1)
+    b.record(stream)
+    torch.cuda.synchronize()
+    res = dict(bricks=8, brick_dims=[half] * 3, brick_raycast_kernel_ms=round(ms / max(n, 1), 4),
+               composite_ms=round(a.elapsed_time(b) / reps, 4))
+    log(f"bench: bricks8 {res}")
+    del vols
+    return res
+
+
 def batch64(ctx, steps):
     """The 64-sub-volume workload as one batched launch (hipGraph replay)."""
     import torch
@@ -474,6 +523,7 @@ def main():
         extras["iso"] = iso_frames(ctx, args.n, args.width, args.height)
         extras["encode_rgba8"] = encode(ctx, args.width, args.height)
         extras["jpeg"] = jpeg_frames(ctx, sc)
+        extras["bricks8"] = bricks8(ctx, sc)
         extras["insitu"] = insitu_run(ctx, 128, args.width, args.height)
         extras["batch64"] = batch64(ctx, 10)
         extras["serving"] = serving(ctx, args.serve_seconds, 200.0)
