@@ -257,6 +257,41 @@ def bricks8(ctx, sc, reps: int = 5):
     return res
 
 
+def served_readback(ctx, reps: int = 10, n: int = 512, depth: int = 256):
+    """A served 1920x1080 request on the frozen resident volume, from submission to the image in
+    host memory: as RGBA32F (33 MB over PCIe), as RGBA8 (8 MB) and as JPEG (quality 90)."""
+    import torch
+    from paper_1611_09048_amd import device
+    from scenes import configs
+    dims = (n, n, depth)
+    sc = configs.pic3(dims=dims, width=1920, height=1080)
+    vol = device.upload_volume(ctx, sc, 201)
+    ctx.freeze_volume(201)
+    job = device.render_job(sc, 201, device.new_image(sc))
+    f32 = np.empty((sc.height, sc.width, 4), np.float32)
+    u8 = np.empty((sc.height, sc.width, 4), np.uint8)
+    reads = {"rgba32f": lambda t: ctx.read_image(t, f32),
+             "rgba8": lambda t: ctx.read_image_rgba8(t, u8, (1.0, 1.0, 1.0)),
+             "jpeg": lambda t: ctx.read_image_jpeg(t, sc.width, sc.height, 90, (1.0, 1.0, 1.0))}
+    res = {}
+    for name, read in reads.items():
+        for k in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t = ctx.submit(job)
+            out = read(t)
+            dt = time.perf_counter() - t0
+            ctx.release(t)
+            if k == 0:
+                continue                     # first call: buffers and graphs are set up
+            res.setdefault(name, []).append(dt * 1e3)
+        res[name] = round(float(np.median(res[name])), 3)
+    res["jpeg_bytes"] = len(out)
+    log(f"bench: served readback (ms, submit to host image) {res}")
+    del vol
+    return res
+
+
 def batch64(ctx, steps):
     """The 64-sub-volume workload as one batched launch (hipGraph replay)."""
     import torch
@@ -529,6 +564,7 @@ def main():
         extras["serving"] = serving(ctx, args.serve_seconds, 200.0)
         extras["serving_stress"] = serving(ctx, max(2.0, args.serve_seconds / 2), 2000.0)
         extras["serving_unfrozen"] = serving(ctx, max(2.0, args.serve_seconds / 2), 200.0, freeze=False)
+        extras["served_readback_ms"] = served_readback(ctx)
         out["extras"] = extras
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
