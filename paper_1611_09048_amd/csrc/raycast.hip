@@ -1018,7 +1018,7 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         RaySetup R;
         bool hit;
         if (J.rays) {
-            // set up by ray_setup_dense_kernel, one lane per ray
+            // set up by the prepass, one lane per ray
             hit = false;
             if (in_image) {
                 const int rw = J.cull[2] - J.cull[0] + 1;
@@ -1440,12 +1440,11 @@ __global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
 // into the job's ray records (kb = ke = 0: no scan point); the ray-casting
 // kernel then reads a record instead of repeating the FP64 setup on every
 // lane of a ray's group.
-__global__ __launch_bounds__(256) void ray_setup_dense_kernel(const DevJob* __restrict__ jobs) {
-    const DevJob& J = jobs[blockIdx.y];
+__device__ __forceinline__ void ray_setup_dense(const DevJob& J, int block, int n_blocks) {
     const int rw = J.cull[2] - J.cull[0] + 1, rh = J.cull[3] - J.cull[1] + 1;
     if (rw <= 0 || rh <= 0) return;
     RayRec* rays = static_cast<RayRec*>(J.rays);
-    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < rw * rh; i += (int)(gridDim.x * blockDim.x)) {
+    for (int i = block * 256 + (int)threadIdx.x; i < rw * rh; i += n_blocks * 256) {
         const int ry = i / rw, rx = i - ry * rw;
         const int px = J.cull[0] + rx, py = J.cull[1] + ry;
         RaySetup R;
@@ -1470,16 +1469,30 @@ __global__ __launch_bounds__(256) void ray_setup_dense_kernel(const DevJob* __re
 
 // Clear the output of every pixel outside its job's screen rectangle (no ray
 // there can meet the box): transparent black, 0 samples, depth +inf.
-__global__ void fill_outside_kernel(const DevJob* __restrict__ jobs) {
-    const DevJob& J = jobs[blockIdx.y];
+__device__ __forceinline__ void fill_outside(const DevJob& J, int block, int n_blocks) {
     const int n = J.width * J.height;
-    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x)) {
+    for (int i = block * 256 + (int)threadIdx.x; i < n; i += n_blocks * 256) {
         const int py = i / J.width, px = i - py * J.width;
         if (px >= J.cull[0] && px <= J.cull[2] && py >= J.cull[1] && py <= J.cull[3]) continue;
         reinterpret_cast<float4*>(J.out)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (J.out_samples) J.out_samples[i] = 0;
         if (J.out_depth) J.out_depth[i] = __builtin_inff();
     }
+}
+
+__global__ __launch_bounds__(256) void fill_outside_kernel(const DevJob* __restrict__ jobs) {
+    fill_outside(jobs[blockIdx.y], (int)blockIdx.x, (int)gridDim.x);
+}
+
+// The fill and the ray setup touch different memory: one launch runs both,
+// workgroups [0, nb) filling and [nb, 2 nb) setting up rays.
+__global__ __launch_bounds__(256) void prepass_kernel(const DevJob* __restrict__ jobs, int nb) {
+    const DevJob& J = jobs[blockIdx.y];
+    const int b = (int)blockIdx.x;
+    if (b < nb)
+        fill_outside(J, b, nb);
+    else
+        ray_setup_dense(J, b - nb, nb);
 }
 
 __global__ void reset_counter_kernel(int* c, int n) {
@@ -1558,10 +1571,11 @@ KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
 
 int launch_prepass(const LaunchArgs& a, void* stream) {
     // pixels outside the jobs' screen rectangles, then (optionally) the rays inside them
-    hipLaunchKernelGGL(fill_outside_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0, (hipStream_t)stream,
-                       a.jobs);
     if (a.dense_setup)
-        hipLaunchKernelGGL(ray_setup_dense_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0,
+        hipLaunchKernelGGL(prepass_kernel, dim3(2 * a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0,
+                           (hipStream_t)stream, a.jobs, (int)a.fill_blocks);
+    else
+        hipLaunchKernelGGL(fill_outside_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0,
                            (hipStream_t)stream, a.jobs);
     return hipGetLastError();
 }
