@@ -637,6 +637,7 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
     dj.h = cb.h;
     dj.aspect = cb.aspect;
     dj.step = j.step;
+    dj.half_step = 0.5f * (float)dj.step;
     dj.ortho = j.projection == ISAAC_ORTHOGRAPHIC;
     dj.width = j.width;
     dj.height = j.height;
@@ -660,12 +661,14 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
                 j.global_dims[a] > (1 << 22))
                 return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "brick axis %d lies outside the global box", a);
             dj.org[a] = (float)j.brick_origin[a];
+            dj.orgh[a] = (float)j.brick_origin[a] + 0.5f;
             dj.gbox_hi[a] = (double)j.global_dims[a];
         }
         dj.brick = 1;
     } else {
         for (int a = 0; a < 3; ++a) {
             dj.org[a] = 0.0f;
+            dj.orgh[a] = 0.5f;
             dj.gbox_hi[a] = (double)v.dims[a];
         }
         dj.brick = 0;

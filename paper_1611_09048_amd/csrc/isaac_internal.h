@@ -78,6 +78,8 @@ struct DevJob {
     double clip[kMaxClip][4];
     double gbox_hi[3];     // the global box [0, gbox_hi] the step grid is anchored to
     float org[3];          // index of this volume's voxel (0,0,0) in the global box (bricks)
+    float orgh[3];         // org + 1/2, exact: trilinear cell coordinates are the position minus orgh
+    float half_step;       // (float)step / 2, exact
     int32_t brick;         // 1: this volume is a brick of a larger global volume
     int32_t ortho;
     int32_t width, height;

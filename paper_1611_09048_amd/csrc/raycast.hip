@@ -224,8 +224,11 @@ __device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], 
 }
 
 // Transfer-table lookup: clamp to [0,1] (NaN -> 0), 255 intervals, linear.
+// No contraction: the fraction is u - j of the rounded u in every caller,
+// whatever the surrounding code lets the compiler fuse.
 __device__ __forceinline__ float4 classify(const float4* __restrict__ table, float x) {
-    float t = (x > 0.f) ? fminf(x, 1.f) : 0.f;
+#pragma clang fp contract(off)
+    float t = fminf(fmaxf(x, 0.f), 1.f);    // max(NaN, 0) = 0
     float u = 255.f * t;
     int j = min((int)u, 254);
     float f = u - (float)j;
@@ -261,6 +264,19 @@ __device__ __forceinline__ void point_at(const DevJob& J, const RaySetup& R, flo
     p[0] = fmaf(tk, R.d[0], R.pb[0]) - J.org[0];
     p[1] = fmaf(tk, R.d[1], R.pb[1]) - J.org[1];
     p[2] = fmaf(tk, R.d[2], R.pb[2]) - J.org[2];
+}
+
+// Trilinear cell coordinates u = p - 1/2 of scan point k in index space:
+// the numbers point_at at (k + 1/2) step gives, minus 1/2, bit for bit, in
+// fewer operations.  (k + 1/2) step and k step + step/2 are the same real
+// number, rounded once either way; position - org is exact (an integer origin
+// below 2^22, a position at most a voxel outside the brick), so subtracting
+// org + 1/2 at once rounds the same value as subtracting org, then 1/2.
+__device__ __forceinline__ void cell_at(const DevJob& J, const RaySetup& R, int k, float (&u)[3]) {
+    const float tk = fmaf((float)k, (float)J.step, J.half_step);
+    u[0] = fmaf(tk, R.d[0], R.pb[0]) - J.orgh[0];
+    u[1] = fmaf(tk, R.d[1], R.pb[1]) - J.orgh[1];
+    u[2] = fmaf(tk, R.d[2], R.pb[2]) - J.orgh[2];
 }
 
 __device__ __forceinline__ bool setup_ray(const DevJob& J, int px, int py, RaySetup& R) {
@@ -529,7 +545,7 @@ __device__ __forceinline__ void point_generic(const DevJob& J, const float4* __r
         const float x = sample_source<INTERP>(src, dims, p);
         const float4 c = classify(s_tf + s * kTfRows, x);
         const float wa = src.weight * c.w;
-        S += wa;
+        S = fmaf(src.weight, c.w, S);
         E[0] = fmaf(wa, c.x, E[0]);
         E[1] = fmaf(wa, c.y, E[1]);
         E[2] = fmaf(wa, c.z, E[2]);
@@ -567,18 +583,17 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = min(k + u, R.ke - 1);
-            const float tk = ((float)kk + 0.5f) * step;
             float p[3];
-            point_at(J, R, tk, p);
+            if (INTERP == 0) point_at(J, R, ((float)kk + 0.5f) * step, p);
+            else cell_at(J, R, kk, p);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (INTERP == 0) {
                     i0[u][a] = clampi((int)floorf(p[a]), 0, dims[a] - 1);
                     wts[u][a] = 0.f;
                 } else {
-                    const float uu = p[a] - 0.5f;
-                    const float fl = floorf(uu);
-                    wts[u][a] = uu - fl;
+                    const float fl = floorf(p[a]);
+                    wts[u][a] = p[a] - fl;
                     i0[u][a] = (int)fl;
                 }
             }
@@ -588,7 +603,7 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
         auto accumulate = [&](int u, int s, float x) {
             const float4 cl = classify(s_tf + s * kTfRows, x);
             const float wa = J.src[s].weight * cl.w;
-            S[u] += wa;
+            S[u] = fmaf(J.src[s].weight, cl.w, S[u]);
             E[u][0] = fmaf(wa, cl.x, E[u][0]);
             E[u][1] = fmaf(wa, cl.y, E[u][1]);
             E[u][2] = fmaf(wa, cl.z, E[u][2]);
@@ -759,11 +774,16 @@ __device__ __forceinline__ bool row_composite(const DevJob& J, const RaySetup& R
     group_scan<G>(lane, c0, c1, c2, a);
     const float T = 1.f - acc.A;
     const float n0 = fmaf(T, c0, acc.C0), n1 = fmaf(T, c1, acc.C1), n2 = fmaf(T, c2, acc.C2), na = fmaf(T, a, acc.A);
-    const unsigned long long m = __ballot(valid && na >= J.ert);
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(na >= J.ert) & __builtin_amdgcn_ballot_w64(valid);
     constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull);
     const unsigned long long bits = (m >> (lane & ~(G - 1))) & kGroupMask;
     const bool stop = bits != 0;
-    const int sel = stop ? __builtin_ctzll(bits) : min(G, R.ke - k0) - 1;
+    // the first terminating point, else the row's last kept one (k0 < R.ke, so
+    // last >= 0; every set bit belongs to a kept point, i.e. lies at or below last)
+    const int last = min(G, R.ke - k0) - 1;
+    int sel;
+    if constexpr (G <= 32) sel = __builtin_ctz((unsigned)bits | (1u << last));
+    else sel = __builtin_ctzll(bits | (1ull << last));
     acc.n += sel + 1;
     acc.C0 = __shfl(n0, sel, G);
     acc.C1 = __shfl(n1, sel, G);
@@ -794,18 +814,17 @@ __device__ __forceinline__ bool lanes_row(const DevJob& J, const float4* __restr
 template <int INTERP>
 __device__ __forceinline__ void il3_locate(const DevJob& J, const RaySetup& R, int k, int (&i0)[3], float (&w)[3]) {
     const int kk = min(k, R.ke - 1);
-    const float tk = ((float)kk + 0.5f) * (float)J.step;
     float p[3];
-    point_at(J, R, tk, p);
+    if (INTERP == 0) point_at(J, R, ((float)kk + 0.5f) * (float)J.step, p);
+    else cell_at(J, R, kk, p);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (INTERP == 0) {
             i0[a] = clampi((int)floorf(p[a]), 0, J.dims[a] - 1);
             w[a] = 0.f;
         } else {
-            const float uu = p[a] - 0.5f;
-            const float fl = floorf(uu);
-            w[a] = uu - fl;
+            const float fl = floorf(p[a]);
+            w[a] = p[a] - fl;
             i0[a] = (int)fl;
         }
     }
@@ -823,7 +842,7 @@ __device__ __forceinline__ void il3_mix(const DevJob& J, const float4* __restric
         for (int i = 0; i < NV; ++i) c[i] = v[i][s];
         const float4 cl = classify(s_tf + s * kTfRows, blend<NV>(c, w));
         const float wa = J.src[s].weight * cl.w;
-        S += wa;
+        S = fmaf(J.src[s].weight, cl.w, S);
         E[0] = fmaf(wa, cl.x, E[0]);
         E[1] = fmaf(wa, cl.y, E[1]);
         E[2] = fmaf(wa, cl.z, E[2]);
