@@ -85,10 +85,31 @@ def test_random_small_scenes(ctx, chunk):
         compare(img2.reshape(-1, 4), cnt2.reshape(-1), rec2, label=f"random_small[{seed}] no-termination")
 
 
+def bench_shape(ctx, sc):
+    """Set the committed tuned tile shape the benchmark uses for this scene's size
+    class and storage type; returns a function that restores the previous one."""
+    import os
+    from paper_1611_09048_amd import autotune
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = autotune.load_cache(os.path.join(root, "paper_1611_09048_amd", "tuned_gfx950.json"))
+    cls = autotune.size_class(sc.width, sc.height)
+    shape = cache.get(autotune.cache_key("gfx950", str(cls), f"pic3:{sc.sources[0].dtype}"))
+    old = ctx.get_tile_shape(cls)
+    if shape is not None:
+        ctx.set_tile_shape(cls, *shape)
+    log("tile shape", cls, shape)
+    return lambda: ctx.set_tile_shape(cls, *old)
+
+
 def test_pic3_full_size_sampled(ctx):
-    """256^3, three sources, 1920x1080 in the benchmark's launch configuration; sampled pixels."""
+    """256^3, three sources, 1920x1080 in the benchmark's launch configuration (its
+    tuned tile shape, derived volume); sampled pixels."""
     sc = configs.pic3()
-    img, cnt = gpu_render(ctx, sc)
+    restore = bench_shape(ctx, sc)
+    try:
+        img, cnt = gpu_render(ctx, sc)
+    finally:
+        restore()
     rng = np.random.default_rng(0)
     px = pixel_list(sc.height, sc.width, 1500, rng, extra_rows=(540,), extra_cols=(960,),
                     hit_mask=img[..., 3] > 0, n_hit=2500)
@@ -104,7 +125,11 @@ def test_pic3_full_size_sampled(ctx):
 def test_pic3_4k_sampled(ctx):
     """The benchmark volume at 3840x2160 (four times the pixels and tiles of 1080p); sampled pixels."""
     sc = configs.pic3(width=3840, height=2160, direction=(0.3, 0.5, -0.8))
-    img, cnt = gpu_render(ctx, sc)
+    restore = bench_shape(ctx, sc)
+    try:
+        img, cnt = gpu_render(ctx, sc)
+    finally:
+        restore()
     rng = np.random.default_rng(4)
     px = pixel_list(sc.height, sc.width, 1000, rng, extra_rows=(1080, 2159), extra_cols=(1920, 3839),
                     hit_mask=img[..., 3] > 0, n_hit=2000)
@@ -112,6 +137,38 @@ def test_pic3_4k_sampled(ctx):
     stats = compare(img[px[:, 1], px[:, 0]], cnt[px[:, 1], px[:, 0]], rec, label="pic3 256^3 4K sampled")
     assert stats["samples"] > 1e5
     assert np.isfinite(img).all()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_pic3_reduced_precision_full_size_sampled(ctx, dtype):
+    """The benchmark scene with FP16 / BF16 storage at 256^3, 1920x1080, in the
+    benchmark's launch configuration: parity against the oracle on the stored
+    values at sampled pixels, and the per-channel max and RMS error against the
+    oracle of the FP32 fields reported beside the FP32-storage run's."""
+    sc = configs.pic3(dtype=dtype)
+    sc32 = configs.pic3()
+    rng = np.random.default_rng(7)
+    restore = bench_shape(ctx, sc)
+    try:
+        img, cnt = gpu_render(ctx, sc)
+    finally:
+        restore()
+    restore = bench_shape(ctx, sc32)
+    try:
+        img32, _ = gpu_render(ctx, sc32)
+    finally:
+        restore()
+    px = pixel_list(sc.height, sc.width, 600, rng, extra_rows=(540,), hit_mask=img[..., 3] > 0, n_hit=1500)
+    rec = oracle.render_pixels(sc, px)
+    g = img[px[:, 1], px[:, 0]]
+    stats = compare(g, cnt[px[:, 1], px[:, 0]], rec, label=f"pic3 256^3 1080p {dtype} sampled")
+    assert stats["samples"] > 5e4
+    ref32 = oracle.render_pixels(sc32, px)["rgba"].reshape(-1, 4)
+    for name, v in ((dtype, g), ("f32", img32[px[:, 1], px[:, 0]])):
+        d = np.abs(v.reshape(-1, 4).astype(np.float64) - ref32)
+        log(f"{name} storage vs FP32-field oracle (1080p sampled): max {d.max(axis=0).tolist()} "
+            f"rms {np.sqrt((d ** 2).mean(axis=0)).tolist()}")
+    assert np.isfinite(img).all() and img.min() >= 0.0 and img.max() <= 1.0 + 1e-6
 
 
 def test_closed_form_slab_on_gpu(ctx):
