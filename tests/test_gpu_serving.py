@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import compare, log
+from parity import compare, log, pixel_list
 from scenes import configs
 
 pytestmark = pytest.mark.gpu
@@ -92,3 +92,53 @@ def test_admission_refused_when_budget_is_full(ctx):
     assert ctx.serving_usage()[0] == 0
     assert ctx.submit(job) is not None
     del vol
+
+
+def test_served_full_size_sampled():
+    """The serving workload at its real sizes: the 512x512x256 three-source volume,
+    frozen as the benchmark serves it, one request at each resolution (512x512,
+    1280x720, 1920x1080) through the continuous-batching loop; every served image
+    compared with the oracle on sampled pixels."""
+    from paper_1611_09048_amd import Context, device, serve
+    from scenes.layout import Camera
+    c = Context(device=0)
+    try:
+        dims = (512, 512, 256)
+        vol_scene = configs.pic3(dims=dims, width=16, height=16)
+        vol = device.upload_volume(c, vol_scene, 200)
+        c.freeze_volume(200)
+        ex = serve.DeviceExecutor(c, vol, dims)
+        images, jobs = {}, {}
+
+        def on_done(rec, ticket):
+            images[rec.rid] = c.read_image(ticket, np.empty((rec.height, rec.width, 4), dtype=np.float32))
+
+        def make_job(i, r):
+            jobs[i] = serve.job_from_request(i, r)
+            return jobs[i]
+
+        srv = serve.Server(ex, time.perf_counter, max_batch=16, max_batches_in_flight=3, on_done=on_done)
+        reqs = configs.serving_requests(11, dims, n_clients=4, rate_per_client=200.0, duration=0.05,
+                                        base_tfs=[s.tf for s in vol_scene.sources])
+        sizes = [(512, 512), (1280, 720), (1920, 1080)]
+        reqs = [r.__class__(**{**r.__dict__, "width": sizes[i][0], "height": sizes[i][1]})
+                for i, r in enumerate(reqs[:3])]
+        assert len(reqs) == 3
+        dur = serve.run(srv, reqs, time.perf_counter, make_job=make_job)
+        summary = srv.summary(dur)
+        log("full-size serving summary", summary)
+        assert summary["completed"] == 3 and summary["failed"] == 0
+        rng = np.random.default_rng(12)
+        for rid, j in jobs.items():
+            eye, center, up = ex.camera(j.direction)
+            srcs = [s.__class__(**{**s.__dict__, "tf": j.tfs[k]}) for k, s in enumerate(vol_scene.sources)]
+            sc = vol_scene.with_(sources=srcs, camera=Camera(eye=eye, center=center, up=up), width=j.width,
+                                 height=j.height, clip=j.clip)
+            img = images[rid]
+            assert np.isfinite(img).all()
+            px = pixel_list(j.height, j.width, 300, rng, hit_mask=img[..., 3] > 0, n_hit=700)
+            rec = oracle.render_pixels(sc, px)
+            compare(img[px[:, 1], px[:, 0]], None, rec, label=f"served {j.width}x{j.height} request {rid}")
+        del vol
+    finally:
+        c.close()
