@@ -518,8 +518,10 @@ __device__ __forceinline__ float blend(const float (&c)[N], const float (&w)[3])
 // for a compile-time source signature, issuing every load before any is
 // consumed (the source loop unrolled at compile time, as the paper does with
 // template metaprogramming, Sec. 3.2).  Both return the mixed premultiplied
-// colour E and opacity S of each point and share the arithmetic operation for
-// operation, so they give the same image bit for bit.
+// colour E and opacity S of each point and round alike at every step (the
+// trilinear cell coordinates come from point_at and a subtraction of 1/2 in
+// one, from cell_at in the other, which give the same numbers), so they give
+// the same image bit for bit.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void mix_finish(float& S, float (&E)[3]) {
     if (S > 1.f) {
