@@ -58,18 +58,24 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1611_09048_amd", "csrc", "raycast.hip")
 
 def measured_traffic():
     """HBM bytes per launch of the ray-casting kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+    summary, or None when the kernel source or the tuner cache (which sets the
+    launch's tile shape) changed since it was taken."""
     import hashlib
     try:
         text = open(COUNTERS).read()
         src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        tuned = hashlib.sha256(open(TUNED, "rb").read()).hexdigest()
     except OSError:
         return None
-    sha = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("kernel source sha256:")]
-    val = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("traffic_bytes_per_launch:")]
-    if not sha or not val or sha[0] != src:
+
+    def field(name):
+        v = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith(name + ":")]
+        return v[0] if v else None
+
+    val = field("traffic_bytes_per_launch")
+    if field("kernel source sha256") != src or field("tuner cache sha256") != tuned or val is None:
         return None
-    return int(val[0])
+    return int(val)
 
 
 def cpu_baseline(scene, gpu_counts, row_stride: int, threads: int):
