@@ -235,7 +235,7 @@ isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const
 isaac_status isaac_freeze_volume(isaac_context* ctx, int volume_id);
 
 /* Frame encode (the step after compositing, where the root rank compresses
- * the image before sending it, Sec. 3.4): each pixel of a premultiplied
+ * the image before sending it, Sec. 3.6): each pixel of a premultiplied
  * RGBA32F image (device, width*height*4 floats) is quantized to 8 bits per
  * channel into out (device, width*height*4 bytes, row 0 on top):
  *   background == NULL: (q(C_r), q(C_g), q(C_b), q(A)), still premultiplied;
@@ -248,7 +248,7 @@ isaac_status isaac_encode_rgba8(isaac_context* ctx, const float* rgba, int width
                                 const float* background, unsigned char* out, unsigned flags);
 
 /* JPEG compression of an RGBA8 frame, the form in which the root rank sends
- * the composited image to the server (Sec. 3.4).  The paper leaves the
+ * the composited image to the server (Sec. 3.6).  The paper leaves the
  * encoder open; this one writes baseline sequential JPEG (JFIF 1.01):
  *  - colour: Y, Cb, Cr from R, G, B (alpha ignored) with the JFIF weights in
  *    16-bit fixed point, each rounded half up by a shift; no subsampling;
@@ -337,7 +337,7 @@ isaac_status isaac_read_image_rgba8(isaac_context* ctx, uint64_t ticket, const f
 
 /* Encode a ticket's image to RGBA8 as isaac_read_image_rgba8 does, then to
  * JPEG as isaac_encode_jpeg does (waiting for both): what the root rank sends
- * to the server (Sec. 3.4). */
+ * to the server (Sec. 3.6). */
 isaac_status isaac_read_image_jpeg(isaac_context* ctx, uint64_t ticket, const float* background, int quality,
                                    unsigned char* out, size_t capacity, size_t* out_size);
 

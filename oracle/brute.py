@@ -112,6 +112,38 @@ def _norm(v):
 
 def render(scene):
     """Returns (image[h][w][4] as nested lists, samples[h][w])."""
+    out = render_flagged(scene, None, None)
+    return out["image"], out["samples"]
+
+
+def _nearest_alternatives(p, dims, delta):
+    """Cells and flagged axes of the nearest-cell decision at p: per axis the cell
+    floor(p) (clamped) and, when p lies closer than delta to an interior cell
+    boundary b (1 <= b <= n-1), the cell on the other side of b."""
+    cell, other = [], []
+    for a in range(3):
+        c = min(max(int(math.floor(p[a])), 0), dims[a] - 1)
+        cell.append(c)
+        b = int(math.floor(p[a] + 0.5))            # the boundary nearest to p
+        if 1 <= b <= dims[a] - 1 and abs(p[a] - b) < delta:
+            other.append((a, b - 1 if c == b else b))
+    return cell, other
+
+
+def render_flagged(scene, delta, ert_margin):
+    """The ray caster with the decision bookkeeping of the several-correct-results
+    reading: a decision taken within `delta` voxels of a clip plane (distance
+    |n.p + d| / |n|), of the box exit (|t1 - t| along the ray) or of an interior
+    nearest-cell boundary, or with an opacity within `ert_margin` of the
+    termination threshold, may go the other way; each such decision adds to the
+    pixel's allowance the most it can change the result.  A scan point kept or
+    dropped near a plane or the exit changes the composite by its own
+    contribution T (|E|max + S), T the transmittance in front of it, and the
+    sample count by one; a nearest cell near a boundary by T times the largest
+    change (|dE|max + |dS|) over the alternative cells; stopping or going on at
+    the threshold by 1 - A.  delta=None: no bookkeeping (plain render).
+
+    Returns dict(image, samples, allowance, flags, count_slack) as nested lists."""
     cam = scene.camera
     nx, ny, nz = scene.dims
     dims = (nx, ny, nz)
@@ -126,13 +158,53 @@ def render(scene):
     for s in scene.sources:
         table = [pl(s.tf, j / 255.0) for j in range(256)]
         srcs.append((s, parse_chain(s.chain, s.f_dim), table))
+    bookkeeping = delta is not None
 
     def value(s, ops, x, y, z):
         g = s.guard
         return apply_chain(ops, [float(s.values[z + g, y + g, x + g, c]) for c in range(s.f_dim)])
 
+    def point(p, cell=None):
+        """Mixed premultiplied colour E and opacity S at p (cell overrides the nearest cell)."""
+        S, E = 0.0, [0.0, 0.0, 0.0]
+        for s, ops, table in srcs:
+            if not s.enabled:
+                continue
+            if scene.interpolation == 0:
+                q = cell if cell is not None else [min(max(int(math.floor(p[a])), 0), dims[a] - 1)
+                                                   for a in range(3)]
+                val = value(s, ops, *q)
+            else:
+                u = [p[a] - 0.5 for a in range(3)]
+                i0 = [int(math.floor(u[a])) for a in range(3)]
+                f = [u[a] - i0[a] for a in range(3)]
+                val = 0.0
+                for cz in (0, 1):
+                    for cy in (0, 1):
+                        for cx in (0, 1):
+                            q = [i0[0] + cx, i0[1] + cy, i0[2] + cz]
+                            if s.guard < 1:
+                                q = [min(max(q[a], 0), dims[a] - 1) for a in range(3)]
+                            w = ((f[0] if cx else 1.0 - f[0]) * (f[1] if cy else 1.0 - f[1])
+                                 * (f[2] if cz else 1.0 - f[2]))
+                            val += w * value(s, ops, *q)
+            r, g, b, al = classify(table, val)
+            wa = s.weight * al
+            S += wa
+            E = [E[0] + wa * r, E[1] + wa * g, E[2] + wa * b]
+        if S > 1.0:
+            E = [e / S for e in E]
+            S = 1.0
+        return E, S
+
+    def change(E, S, E2, S2):
+        return max(abs(E[c] - E2[c]) for c in range(3)) + abs(S - S2)
+
     img = [[[0.0] * 4 for _ in range(W)] for _ in range(H)]
     cnt = [[0] * W for _ in range(H)]
+    allow = [[0.0] * W for _ in range(H)]
+    nflags = [[0] * W for _ in range(H)]
+    slack = [[0] * W for _ in range(H)]
     for j in range(H):
         for i in range(W):
             x = (2.0 * (i + 0.5) / W - 1.0) * h * aspect
@@ -155,47 +227,61 @@ def render(scene):
             if not hit or not t1 > t0:
                 continue
             C, A, n, k = [0.0, 0.0, 0.0], 0.0, 0, 0
+            al, nf, sl = 0.0, 0, 0
             while True:
                 t = t0 + (k + 0.5) * scene.step
                 k += 1
-                if not t < t1:
+                inside = t < t1
+                # a point just past the exit is only looked at for the bookkeeping
+                if not inside and not (bookkeeping and t - t1 < delta):
                     break
                 p = [o[a] + t * d[a] for a in range(3)]
-                if any(pc[0] * p[0] + pc[1] * p[1] + pc[2] * p[2] + pc[3] < 0.0 for pc in scene.clip):
+                clipped = any(pc[0] * p[0] + pc[1] * p[1] + pc[2] * p[2] + pc[3] < 0.0 for pc in scene.clip)
+                keep = inside and not clipped
+                near = False
+                if bookkeeping:
+                    near = abs(t1 - t) < delta or any(
+                        abs(pc[0] * p[0] + pc[1] * p[1] + pc[2] * p[2] + pc[3])
+                        < delta * math.sqrt(pc[0] ** 2 + pc[1] ** 2 + pc[2] ** 2) for pc in scene.clip)
+                if not keep:
+                    if near:                         # kept on the other side
+                        E, S = point(p)
+                        al += (1.0 - A) * (max(abs(e) for e in E) + abs(S))
+                        nf += 1
+                        sl += 1
+                    if not inside:
+                        break
                     continue
-                S, E = 0.0, [0.0, 0.0, 0.0]
-                for s, ops, table in srcs:
-                    if not s.enabled:
-                        continue
-                    if scene.interpolation == 0:
-                        q = [min(max(int(math.floor(p[a])), 0), dims[a] - 1) for a in range(3)]
-                        val = value(s, ops, *q)
-                    else:
-                        u = [p[a] - 0.5 for a in range(3)]
-                        i0 = [int(math.floor(u[a])) for a in range(3)]
-                        f = [u[a] - i0[a] for a in range(3)]
-                        val = 0.0
-                        for cz in (0, 1):
-                            for cy in (0, 1):
-                                for cx in (0, 1):
-                                    q = [i0[0] + cx, i0[1] + cy, i0[2] + cz]
-                                    if s.guard < 1:
-                                        q = [min(max(q[a], 0), dims[a] - 1) for a in range(3)]
-                                    w = ((f[0] if cx else 1.0 - f[0]) * (f[1] if cy else 1.0 - f[1])
-                                         * (f[2] if cz else 1.0 - f[2]))
-                                    val += w * value(s, ops, *q)
-                    r, g, b, al = classify(table, val)
-                    wa = s.weight * al
-                    S += wa
-                    E = [E[0] + wa * r, E[1] + wa * g, E[2] + wa * b]
-                if S > 1.0:
-                    E = [e / S for e in E]
-                    S = 1.0
+                E, S = point(p)
+                if near:                             # dropped on the other side
+                    al += (1.0 - A) * (max(abs(e) for e in E) + abs(S))
+                    nf += 1
+                    sl += 1
+                if bookkeeping and scene.interpolation == 0:
+                    cell, other = _nearest_alternatives(p, dims, delta)
+                    if other:
+                        worst = 0.0
+                        for mask in range(1, 1 << len(other)):
+                            q = list(cell)
+                            for b, (a, c2) in enumerate(other):
+                                if mask >> b & 1:
+                                    q[a] = c2
+                            E2, S2 = point(p, q)
+                            worst = max(worst, change(E, S, E2, S2))
+                        al += (1.0 - A) * worst
+                        nf += 1
                 C = [C[c] + (1.0 - A) * E[c] for c in range(3)]
                 A = A + (1.0 - A) * S
                 n += 1
                 if A >= scene.ert_threshold:
+                    if bookkeeping and A - scene.ert_threshold < ert_margin:   # might go on
+                        al += 1.0 - A
+                        nf += 1
                     break
+                if bookkeeping and scene.ert_threshold - A < ert_margin:        # might stop here
+                    al += 1.0 - A
+                    nf += 1
             img[j][i] = [C[0], C[1], C[2], A]
             cnt[j][i] = n
-    return img, cnt
+            allow[j][i], nflags[j][i], slack[j][i] = al, nf, sl
+    return dict(image=img, samples=cnt, allowance=allow, flags=nflags, count_slack=slack)

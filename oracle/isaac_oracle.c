@@ -555,7 +555,61 @@ static void render_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
 /* interpolation, the normal is the central-difference gradient (half a  */
 /* voxel), and the opaque pixel is the TF colour at the iso value lit by */
 /* a headlight: rgb * (0.3 + 0.7 |n . d|), opacity 1.                    */
+/*                                                                       */
+/* Decisions within their margins (a kept/dropped scan point near a clip */
+/* plane or the box exit, a nearest cell near a boundary, a value near   */
+/* the iso value) may go either way in FP32.  The crossing, and with it  */
+/* the whole pixel, can move only when the other outcome                 */
+/*   - puts some source's value on the other side of its iso value      */
+/*     (an iso-margin value; a nearest cell whose alternative lies on    */
+/*     the other side; a dropped scan point whose kept value differs in  */
+/*     side from a kept neighbour), or                                   */
+/*   - changes one of the two scan points the crossing is placed between, */
+/*     or a cell the gradient reads;                                     */
+/* such a pixel is unconstrained (allowance 2, any sample count).  Other */
+/* flagged decisions only move the count by one (a kept scan point that  */
+/* might be dropped, or the reverse, away from the crossing).            */
 /* ------------------------------------------------------------------ */
+#define ISO_FREE_COUNT (1 << 30)
+
+/* side of each surfaced source's value: bit s set when x[s] >= iso */
+static unsigned iso_sides(const prepared* P, const double* x) {
+    unsigned m = 0;
+    for (int s = 0; s < P->sc->n_src; s++) {
+        const oracle_source* src = &P->sc->src[s];
+        if (!src->enabled || isnan(src->iso)) continue;
+        if (x[s] >= src->iso) m |= 1u << s;
+    }
+    return m;
+}
+
+static void iso_values(const prepared* P, const double p[3], const int* cell, double* x) {
+    for (int s = 0; s < P->sc->n_src; s++) {
+        const oracle_source* src = &P->sc->src[s];
+        x[s] = 0.0;
+        if (!src->enabled || isnan(src->iso)) continue;
+        x[s] = source_at(P, s, p, cell);
+    }
+}
+
+/* How far source s's value at p can move in FP32 evaluation: the position
+ * may be off by up to delta voxels per axis (the value then moves by at most
+ * the larger change over +-delta along each axis, summed over the axes; the
+ * interpolant is multilinear per cell), and the arithmetic by a small
+ * relative amount (iso_margin relative to the value's magnitude). */
+static double iso_value_margin(const prepared* P, int s, const double p[3], double x) {
+    double m = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double q[3] = {p[0], p[1], p[2]};
+        q[a] = p[a] + P->sc->delta;
+        double up = fabs(source_at(P, s, q, NULL) - x);
+        q[a] = p[a] - P->sc->delta;
+        double dn = fabs(source_at(P, s, q, NULL) - x);
+        m += up > dn ? up : dn;
+    }
+    return m + P->sc->iso_margin * (1.0 + fabs(x));
+}
+
 static void iso_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
     const oracle_scene* sc = P->sc;
     memset(px, 0, sizeof(*px));
@@ -566,41 +620,91 @@ static void iso_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
     double prev[MAX_SRC];
     double t_prev = 0.0;
     int have_prev = 0;
+    int unconstrained = 0;        /* some flagged decision can move the crossing */
+    int prev_flagged = 0;         /* the scan point held in prev[] carries a flagged decision */
+    int pending = 0;              /* a flagged dropped point whose kept value's sides are in pending_sides */
+    unsigned pending_sides = 0;
     for (int64_t k = 0;; k++) {
         double t = scan_param(sc, t0, k);
-        if (!(t < t1)) {
-            if (t - t1 < delta) { px->kinds |= ORACLE_FLAG_EXIT; px->flags++; }
-            break;
-        }
-        if (t1 - t < delta) { px->kinds |= ORACLE_FLAG_EXIT; px->flags++; }
+        int inside = t < t1;
+        if (!inside && !(t - t1 < delta)) break;
         double p[3];
         for (int a = 0; a < 3; a++) p[a] = o[a] + t * d[a];
         int near_plane;
-        int keep = clip_keep(sc, p, &near_plane);
-        if (near_plane) { px->kinds |= ORACLE_FLAG_CLIP; px->flags++; }
+        int keep = clip_keep(sc, p, &near_plane) && inside;
+        int near_exit = (t1 - t < delta) && (t - t1 < delta);
+        int kind = (near_plane ? ORACLE_FLAG_CLIP : 0) | (near_exit ? ORACLE_FLAG_EXIT : 0);
         if (!keep) {
+            if (kind) {
+                /* kept on the other side: it joins the chain of kept points around it */
+                double xa[MAX_SRC];
+                iso_values(P, p, NULL, xa);
+                unsigned alt = iso_sides(P, xa);
+                if (have_prev && alt != iso_sides(P, prev)) unconstrained = 1;
+                pending = 1;
+                pending_sides = alt;
+                px->flags++;
+                px->kinds |= kind;
+                px->count_slack++;
+            } else {
+                pending = 0;
+            }
             have_prev = 0;
+            prev_flagged = 0;
+            if (!inside) break;
             continue;
         }
-        if (sc->interpolation == 0) {
-            int cell[3], alt[3];
-            if (nearest_flags(P, p, cell, alt)) { px->kinds |= ORACLE_FLAG_NEAREST; px->flags++; }
+        int flagged_here = 0;
+        if (kind) {                                   /* the other side might drop it */
+            px->flags++;
+            px->kinds |= kind;
+            px->count_slack++;
+            flagged_here = 1;
         }
+        double x[MAX_SRC];
+        iso_values(P, p, NULL, x);
+        const unsigned sides = iso_sides(P, x);
+        if (sc->interpolation == 0) {
+            int cell[3], alt[3], mask = nearest_flags(P, p, cell, alt);
+            if (mask) {
+                px->flags++;
+                px->kinds |= ORACLE_FLAG_NEAREST;
+                flagged_here = 1;
+                for (int sub = 1; sub < 8; sub++) {
+                    if ((sub & mask) != sub) continue;
+                    int q[3];
+                    for (int a = 0; a < 3; a++) q[a] = (sub >> a & 1) ? alt[a] : cell[a];
+                    double xa[MAX_SRC];
+                    iso_values(P, p, q, xa);
+                    if (iso_sides(P, xa) != sides) unconstrained = 1;
+                }
+            }
+        }
+        for (int s = 0; s < sc->n_src; s++) {
+            const oracle_source* src = &sc->src[s];
+            if (!src->enabled || isnan(src->iso)) continue;
+            if (fabs(x[s] - src->iso) < iso_value_margin(P, s, p, x[s])) {
+                px->kinds |= ORACLE_FLAG_ISO;
+                px->flags++;
+                unconstrained = 1;
+            }
+        }
+        if (pending && sides != pending_sides) unconstrained = 1;
+        pending = 0;
         px->samples++;
-        double x[MAX_SRC] = {0};
         int hit = -1;
         double f = 0.0;
         for (int s = 0; s < sc->n_src; s++) {
             const oracle_source* src = &sc->src[s];
             if (!src->enabled || isnan(src->iso)) continue;
-            x[s] = source_at(P, s, p, NULL);
-            if (fabs(x[s] - src->iso) < sc->iso_margin) { px->kinds |= ORACLE_FLAG_ISO; px->flags++; }
             if (hit < 0 && have_prev && ((prev[s] >= src->iso) != (x[s] >= src->iso))) {
                 hit = s;
                 f = (src->iso - prev[s]) / (x[s] - prev[s]);
             }
         }
         if (hit >= 0) {
+            /* a flagged decision at either end of the crossing moves it */
+            if (flagged_here || prev_flagged) unconstrained = 1;
             const oracle_source* src = &sc->src[hit];
             double ts = t_prev + f * (t - t_prev), q[3], g[3];
             for (int a = 0; a < 3; a++) q[a] = o[a] + ts * d[a];
@@ -608,6 +712,14 @@ static void iso_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
                 double qp[3] = {q[0], q[1], q[2]}, qm[3] = {q[0], q[1], q[2]};
                 qp[a] += 0.5;
                 qm[a] -= 0.5;
+                if (sc->interpolation == 0) {
+                    int c1[3], a1[3], c2[3], a2[3];
+                    if (nearest_flags(P, qp, c1, a1) || nearest_flags(P, qm, c2, a2)) {
+                        px->flags++;
+                        px->kinds |= ORACLE_FLAG_NEAREST;
+                        unconstrained = 1;
+                    }
+                }
                 g[a] = source_at(P, hit, qp, NULL) - source_at(P, hit, qm, NULL);
             }
             double gl = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
@@ -622,9 +734,12 @@ static void iso_pixel(const prepared* P, int i, int j, oracle_pixel* px) {
         for (int s = 0; s < sc->n_src; s++) prev[s] = x[s];
         t_prev = t;
         have_prev = 1;
+        prev_flagged = flagged_here;
     }
-    /* a decision within the margins may go either way: the pixel is unconstrained */
-    if (px->flags) px->allowance = 2.0;
+    if (unconstrained) {
+        px->allowance = 2.0;
+        px->count_slack = ISO_FREE_COUNT;
+    }
 }
 
 static int check_scene(const oracle_scene* sc, char* err, int errlen) {

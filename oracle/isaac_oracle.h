@@ -60,7 +60,8 @@ typedef struct {
     const double* clip;               /* n_clip * 4: nx ny nz d, keep n.x + d >= 0 */
     double ert_threshold;             /* stop once accumulated opacity >= this (> 1: never) */
     int mode;                         /* 0 volume rendering, 1 iso-surface rendering */
-    double iso_margin;                /* iso mode: values this close to the iso value flag the pixel */
+    double iso_margin;                /* iso mode: relative arithmetic error of a value (the decision margin of
+                                         the iso comparison adds the value's change over +-delta per axis) */
     double delta;                     /* decision margin for the flip allowance (voxels) */
     double ert_margin;                /* opacity margin for the flip allowance at the threshold */
 } oracle_scene;
@@ -96,7 +97,7 @@ int oracle_tf_table(int n_tf, const double* tf, double* table, char* err, int er
 
 /* Ray of pixel (i, j): origin, unit direction and the box interval [t0, t1]
  * (t0 >= 0); returns 1 if the ray meets the box, 0 otherwise. */
-/* Frame encode (the image is compressed before it is sent, Sec. 3.4): each
+/* Frame encode (the image is compressed before it is sent, Sec. 3.6): each
  * premultiplied RGBA pixel, optionally over an opaque rgb background, is
  * quantized to 8 bits, q(v) = floor(clamp(v,0,1)*255 + 1/2), NaN -> 0.  The
  * quantization is an integer decision, taken here in FP32 with every

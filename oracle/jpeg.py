@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: used by tests/ and nowhere in the library.
 
 The paper compresses the composited image to JPEG on the root rank before
-sending it to the server (Sec. 3.4).  It gives no encoder details, so the
+sending it to the server (Sec. 3.6).  It gives no encoder details, so the
 encoder is defined here (readings recorded with the design notes) in plain
 integer arithmetic, so that every coefficient and every bit is a fixed
 function of the input:

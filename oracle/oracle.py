@@ -49,7 +49,8 @@ NO_TERMINATION = 2.0        # a threshold opacity never reaches
 
 DELTA = 2.0 ** -12          # voxels: decisions closer than this may go either way on the GPU
 ERT_MARGIN = 1e-4           # opacity margin around the termination threshold
-ISO_MARGIN = 1e-3           # iso mode: values this close to the iso value may cross on either side
+ISO_MARGIN = 2.0 ** -16     # iso mode: relative FP32 arithmetic error of a value; with the value's change over
+                            # +-DELTA per axis it bounds how far the GPU's value can lie from the oracle's
 
 _lib = None
 _lock = threading.Lock()

@@ -1,7 +1,7 @@
 // Baseline JPEG encoding of an RGBA8 frame on the device.
 //
 // The paper compresses the composited frame to JPEG before it goes to the
-// server (Sec. 3.4).  Here every data-parallel step runs on the GPU:
+// server (Sec. 3.6).  Here every data-parallel step runs on the GPU:
 //   1. coef:   one wave per MCU (8x8 pixels, three components): colour
 //              conversion, separable integer DCT through LDS, quantisation,
 //              zigzag; 64 int16 per block, blocks in scan order (Y, Cb, Cr per MCU);

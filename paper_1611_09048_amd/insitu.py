@@ -4,7 +4,7 @@ The library visualizes fields that a simulation keeps in device memory, read
 in place through their accessors (zero copy, Sec. 3.1); the simulation and
 the renderer share the accelerator, so the simulation pauses while a frame
 is rendered, and a frame may be rendered only every n-th time step when a
-step is short (Sec. 3.4, the Petri net of the render cycle).  Before each
+step is short (Sec. 3.6, the Petri net of the render cycle).  Before each
 render the library calls every source's update() (Sec. 3.2), which here
 derives a secondary field into a scratch buffer; that source is declared
 non-persistent, so the library copies it before the next source's update

@@ -36,6 +36,7 @@ def compare(gpu_rgba: np.ndarray, gpu_cnt, rec: np.ndarray, tol: float = TOL, la
     stats = dict(label=label, pixels=int(g.shape[0]), max_diff=float(diff.max()) if diff.size else 0.0,
                  max_diff_unflagged=float(diff[~flagged].max()) if (~flagged).any() else 0.0,
                  flagged_pixels=int(flagged.sum()),
+                 unconstrained_pixels=int((rec["allowance"] >= 1.0).sum()),
                  max_allowance_used=float(np.max(np.where(flagged[:, None], diff, 0.0))) if diff.size else 0.0,
                  samples=int(rec["samples"].sum()))
     if bad.any():

@@ -526,6 +526,205 @@ def pin_iso_sphere(lib):
 
 
 # ---------------------------------------------------------------------------
+# several correct results: the allowance of decisions taken within their margins
+# ---------------------------------------------------------------------------
+#
+# Scan points on these axis-aligned orthographic rays sit at x = (k + 1/2) step
+# exactly (the rays enter the box at x = 0 from x = -10).  Steps of the form
+# m / 2^e with (k + 1/2) step = B +- 2^-13 put a scan point half a margin
+# (delta = 2^-12) from a cell boundary, a clip plane or the box exit, or, with
+# 2^-11, two margins away; every position is exact in binary.
+
+_D = oracle.oracle.DELTA
+
+
+def _two_cell_scene(dims_x, boundary, step):
+    """Nearest sampling of a field that is 0.25 left of x = boundary and 0.75 right of it;
+    linear alpha (a_max 0.5), rgb (0.2, 0.6, 0.9)."""
+    dims = (dims_x, 3, 3)
+    v = np.where(np.arange(dims_x) < boundary, 0.25, 0.75).astype(np.float32)
+    v = np.broadcast_to(v[None, None, :], (3, 3, dims_x)).copy()
+    src = make_source("step", v, guard=0, tf=configs.linear_alpha_tf((0.2, 0.6, 0.9), 0.5))
+    cam = configs.axis_camera(dims, axis=0, width=3, height=3, ortho_height=3.0)
+    return Scene(dims=dims, sources=[src], camera=cam, width=3, height=3, step=step, interpolation=0,
+                 ert_threshold=1.0)
+
+
+def pin_allowance_nearest_boundary(lib):
+    # a cell with alpha 0.125 in front (T = 0.875), then a scan point 2^-13 from the boundary:
+    # the other cell changes the colour by 0.9 * 0.25 and the opacity by 0.25
+    expect = 0.875 * (0.9 * 0.25 + 0.25)
+    for dims_x, boundary, step, label in ((2, 1, 2731 / 4096, "1 + 2^-13"), (3, 2, 5461 / 4096, "2 - 2^-13")):
+        assert abs(1.5 * step - boundary) == 2.0 ** -13
+        rec = oracle.render(_two_cell_scene(dims_x, boundary, step), lib=lib)
+        assert np.all(rec["flags"] == 1) and np.all(rec["kinds"] == oracle.oracle.FLAG_NEAREST), label
+        assert np.allclose(rec["allowance"], expect, rtol=0, atol=1e-12), (label, rec["allowance"])
+        assert np.all(rec["count_slack"] == 0)
+    # two margins from the boundary (1 + 2^-11): no decision is in doubt
+    step = 683 / 1024
+    assert 1.5 * step == 1.0 + 2 * _D
+    rec = oracle.render(_two_cell_scene(2, 1, step), lib=lib)
+    assert np.all(rec["flags"] == 0) and np.all(rec["allowance"] == 0.0), rec["allowance"]
+    # trilinear sampling has no nearest-cell decision
+    rec = oracle.render(_two_cell_scene(2, 1, 2731 / 4096).with_(interpolation=1), lib=lib)
+    assert np.all(rec["flags"] == 0) and np.all(rec["allowance"] == 0.0)
+
+
+def pin_allowance_clip_and_exit(lib):
+    # trilinear: no nearest-cell decisions beside the ones under test
+    a, rgb = 0.1, (0.2, 0.6, 0.9)
+    contrib = max(rgb) * a + a                      # |E|max + S of one scan point of the slab
+    eps = 2.0 ** -13
+    # keep x <= 2.75 + eps: the scan point at 2.75 is kept half a margin inside, behind 5 others
+    sc = _slab_scene(interpolation=1, clip=[(-1.0, 0.0, 0.0, 2.75 + eps)])
+    rec, hit = oracle.render(sc, lib=lib), _hit_mask(sc).reshape(-1)
+    assert np.all(_cnt(rec, sc).reshape(-1)[hit] == 6)
+    assert np.allclose(rec["allowance"][hit], 0.9 ** 5 * contrib, rtol=0, atol=1e-12), rec["allowance"][hit]
+    assert np.all(rec["count_slack"][hit] == 1) and np.all(rec["kinds"][hit] == oracle.oracle.FLAG_CLIP)
+    assert np.all(rec["allowance"][~hit] == 0.0) and np.all(rec["flags"][~hit] == 0)
+    # keep x >= 2.75 + eps: the same point is dropped half a margin outside, nothing in front
+    sc = _slab_scene(interpolation=1, clip=[(1.0, 0.0, 0.0, -(2.75 + eps))])
+    rec = oracle.render(sc, lib=lib)
+    assert np.all(_cnt(rec, sc).reshape(-1)[hit] == 10)
+    assert np.allclose(rec["allowance"][hit], contrib, rtol=0, atol=1e-12)
+    assert np.all(rec["count_slack"][hit] == 1)
+    # two margins from the plane: no decision in doubt
+    sc = _slab_scene(interpolation=1, clip=[(-1.0, 0.0, 0.0, 2.75 + 4 * eps)])
+    rec = oracle.render(sc, lib=lib)
+    assert np.all(rec["flags"] == 0) and np.all(rec["allowance"] == 0.0) and np.all(rec["count_slack"] == 0)
+    # the margin is a distance: planes with scaled normals flag exactly the same points
+    for scale, off, flagged in ((4.0, eps, True), (0.25, 4 * eps, False), (0.25, eps, True), (4.0, 4 * eps, False)):
+        sc = _slab_scene(interpolation=1, clip=[(-scale, 0.0, 0.0, scale * (2.75 + off))])
+        rec = oracle.render(sc, lib=lib)
+        want = 0.9 ** 5 * contrib if flagged else 0.0
+        assert np.allclose(rec["allowance"][hit], want, rtol=0, atol=1e-12), (scale, off, rec["allowance"][hit])
+        assert np.all(rec["flags"][hit] == (1 if flagged else 0)), (scale, off)
+    # box exit: a scan point half a margin before the exit face (kept), and one half a margin past it
+    for L, step, n in ((2, 5461 / 4096, 2), (1, 2731 / 4096, 1)):
+        sc = _slab_scene(L=L, step=step, interpolation=1)
+        rec, hit = oracle.render(sc, lib=lib), _hit_mask(sc).reshape(-1)
+        assert abs(1.5 * step - L) == eps
+        assert np.all(_cnt(rec, sc).reshape(-1)[hit] == n), (L, np.unique(rec["samples"]))
+        assert np.allclose(rec["allowance"][hit], 0.9 * contrib, rtol=0, atol=1e-12), (L, rec["allowance"][hit])
+        assert np.all(rec["count_slack"][hit] == 1) and np.all(rec["kinds"][hit] == oracle.oracle.FLAG_EXIT)
+    # trilinear sampling of the slab has no decision within a margin at all (the nearest-cell
+    # camera of the closed-form pins puts one pixel column on a cell boundary)
+    sc = _slab_scene(interpolation=1)
+    rec = oracle.render(sc, lib=lib)
+    assert np.all(rec["flags"] == 0) and np.all(rec["allowance"] == 0.0)
+
+
+def pin_allowance_termination(lib):
+    a10 = 1.0 - 0.9 ** 10                           # opacity after 10 scan points of alpha 0.1
+    a11 = 1.0 - 0.9 ** 11
+    for theta, n, flagged in ((a10 + 5e-5, 11, True), (a10 - 5e-5, 10, True),
+                              (a10 - 5e-4, 10, False), (a10 + 5e-4, 11, False)):
+        sc = _slab_scene(L=40, ert=theta, interpolation=1)
+        rec, hit = oracle.render(sc, lib=lib), _hit_mask(sc).reshape(-1)
+        assert np.all(_cnt(rec, sc).reshape(-1)[hit] == n), (theta, np.unique(rec["samples"]))
+        want = 0.9 ** 10 if flagged else 0.0         # 1 - A at the point next to the threshold
+        assert np.allclose(rec["allowance"][hit], want, rtol=0, atol=1e-12), (theta, rec["allowance"][hit])
+        assert np.all(rec["flags"][hit] == (1 if flagged else 0))
+        assert np.all(rec["count_slack"] == 0)
+    assert a11 - (a10 + 5e-4) > 1e-2                 # the unflagged cases stay outside 100x the margin
+
+
+def pin_allowance_brute_force(lib):
+    """The decision bookkeeping against the brute-force loop's own, with margins magnified
+    (delta 0.05 and 0.2 voxels, opacity margins 0.05 and 0.02) so that every kind of
+    decision occurs many times; and no allowance without a flagged decision."""
+    n_flagged = {1: 0, 2: 0, 4: 0, 8: 0}
+    for seed in range(24):
+        sc = configs.random_small_scene(seed)
+        for delta, em in ((0.05, 0.05), (0.2, 0.02)):
+            rec = oracle.render(sc, delta=delta, ert_margin=em, lib=lib)
+            b = brute.render_flagged(sc, delta, em)
+            assert np.array_equal(np.array(b["samples"]).reshape(-1), rec["samples"]), seed
+            assert np.array_equal(np.array(b["flags"]).reshape(-1), rec["flags"]), seed
+            assert np.array_equal(np.array(b["count_slack"]).reshape(-1), rec["count_slack"]), seed
+            assert np.allclose(np.array(b["allowance"]).reshape(-1), rec["allowance"], rtol=0, atol=1e-12), seed
+            assert np.all(rec["allowance"][rec["flags"] == 0] == 0.0)
+            for k in n_flagged:
+                n_flagged[k] += int(((rec["kinds"] & k) != 0).sum())
+        # at the real margins the same scenes rarely flag anything, and never allow without a flag
+        rec = oracle.render(sc, lib=lib)
+        assert np.all(rec["allowance"][rec["flags"] == 0] == 0.0)
+        assert np.all(rec["count_slack"] <= rec["flags"])
+    assert all(v >= 20 for v in n_flagged.values()), n_flagged
+
+
+def pin_iso_allowance(lib):
+    """Iso mode: a decision within its margin leaves the pixel unconstrained only when it can
+    move the crossing; otherwise it moves at most the sample count."""
+    eps = 2.0 ** -13
+    FREE = 1 << 30
+
+    def centre(rec, sc):
+        return rec[(sc.height // 2) * sc.width + sc.width // 2]
+
+    # the crossing half-way between the scan points at 7.25 and 7.75 (values 1/64 from iso)
+    sc = _iso_ramp_scene((1.0, 0.0, 0.0), 0.5)
+    rec = oracle.render(sc, lib=lib)
+    assert np.all(rec["flags"] == 0) and np.all(rec["allowance"] == 0.0) and np.all(rec["count_slack"] == 0)
+    # the crossing on a scan point (value 0.515625 at x = 7.75 exactly): either side is right
+    sc = _iso_ramp_scene((1.0, 0.0, 0.0), 0.515625)
+    rec = oracle.render(sc, lib=lib)
+    assert np.all(rec["kinds"] & oracle.oracle.FLAG_ISO) and np.all(rec["allowance"] == 2.0)
+    assert np.all(rec["count_slack"] == FREE)
+    # the margin of the iso comparison: the value's change over +-delta per axis (0.0625 delta along
+    # the ramp) plus 2^-16 of its magnitude: 3.84e-5 at the point x = 7.75 (value 0.515625)
+    margin = 0.0625 * _D + 2.0 ** -16 * (1.0 + 0.515625)
+    for off, flagged in ((3e-5, True), (-3e-5, True), (1e-4, False), (-1e-4, False)):
+        assert (abs(off) < margin) == flagged
+        sc = _iso_ramp_scene((1.0, 0.0, 0.0), 0.515625 + off)
+        rec = oracle.render(sc, lib=lib)
+        assert np.all((rec["flags"] > 0) == flagged), (off, np.unique(rec["flags"]))
+        assert np.all(rec["allowance"] == (2.0 if flagged else 0.0)), off
+    # a kink: cell values 0.5 + (4 - i) left of cell 4, 0.5 from it on; one scan point (step
+    # 9 + 2^-12) half a margin right of cell centre 4.5: the value is 0.5 there and to the right,
+    # and rises by 2^-13 over delta to the left, so the margin is the larger, left-hand change
+    dims = (8, 3, 3)
+    xs = np.arange(-1, 9)
+    row = np.where(xs < 4, 0.5 + (4 - xs), 0.5).astype(np.float32)
+    kink = make_source("kink", np.broadcast_to(row[None, None, :], (5, 5, 10)).copy(), guard=1,
+                       tf=configs.constant_tf((0.5, 0.5, 0.5), 1.0))
+    cam = configs.axis_camera(dims, axis=0, width=3, height=3, ortho_height=3.0)
+    margin = 2.0 ** -13 + 2.0 ** -16 * 1.5
+    for off, flagged in ((0.7 * margin, True), (1.3 * margin, False)):
+        kink.iso = 0.5 + off
+        sc = Scene(dims=dims, sources=[kink], camera=cam, width=3, height=3, step=9.0 + 2.0 ** -12,
+                   interpolation=1, ert_threshold=1.0, mode="iso")
+        rec = oracle.render(sc, lib=lib)
+        assert np.all(rec["samples"] == 1)
+        assert np.all((rec["flags"] > 0) == flagged), (off, rec["flags"])
+    base = _iso_ramp_scene((1.0, 0.0, 0.0), 0.5)
+    # a plane half a margin from a kept point far in front of the crossing: count +-1 only
+    for x0 in (2.25 - eps, 2.25 + eps):
+        sc = base.with_(clip=[(1.0, 0.0, 0.0, -x0)])
+        c = centre(oracle.render(sc, lib=lib), sc)
+        assert c["flags"] == 1 and c["allowance"] == 0.0 and c["count_slack"] == 1, (x0, c)
+        assert c["rgba"][3] == 1.0 and c["samples"] == (12 if x0 < 2.25 else 11)
+    # the same at the crossing point (kept or dropped): the crossing moves
+    for x0 in (7.75 + eps, 7.75 - eps):
+        sc = base.with_(clip=[(-1.0, 0.0, 0.0, x0)])
+        c = centre(oracle.render(sc, lib=lib), sc)
+        assert c["flags"] >= 1 and c["allowance"] == 2.0 and c["count_slack"] == FREE, (x0, c)
+    # the point in front of the crossing kept half a margin inside a plane: dropped, the crossing
+    # would have no point in front of it on this side of the plane
+    sc = base.with_(clip=[(1.0, 0.0, 0.0, -(7.25 - eps))])
+    c = centre(oracle.render(sc, lib=lib), sc)
+    assert c["rgba"][3] == 1.0 and c["samples"] == 2 and c["allowance"] == 2.0, c
+    # a dropped point whose kept value would cross with the next kept one (iso between 2.25 and 2.75)
+    sc = _iso_ramp_scene((1.0, 0.0, 0.0), 0.1875).with_(clip=[(1.0, 0.0, 0.0, -(2.25 + eps))])
+    c = centre(oracle.render(sc, lib=lib), sc)
+    assert c["rgba"][3] == 0.0 and c["allowance"] == 2.0, c
+    # two margins away: nothing in doubt
+    sc = _iso_ramp_scene((1.0, 0.0, 0.0), 0.1875).with_(clip=[(1.0, 0.0, 0.0, -(2.25 + 4 * eps))])
+    c = centre(oracle.render(sc, lib=lib), sc)
+    assert c["flags"] == 0 and c["allowance"] == 0.0 and c["count_slack"] == 0, c
+
+
+# ---------------------------------------------------------------------------
 # frame encode: 8-bit quantization of the premultiplied image
 # ---------------------------------------------------------------------------
 
@@ -565,4 +764,5 @@ ALL_PINS = [pin_constant_slab, pin_constant_slab_weight_and_two_sources, pin_mix
             pin_chain_render_equivalence, pin_tf_table, pin_classification_lookup, pin_geometry,
             pin_orientation, pin_perspective_symmetry, pin_brute_force, pin_ert_bound,
             pin_fp16_bf16_reads, pin_iso_plane, pin_iso_bilinear,
-            pin_iso_sphere, pin_encode_rgba8]
+            pin_iso_sphere, pin_encode_rgba8, pin_allowance_nearest_boundary, pin_allowance_clip_and_exit,
+            pin_allowance_termination, pin_allowance_brute_force, pin_iso_allowance]

@@ -63,7 +63,8 @@ def test_iso_matches_oracle(ctx, interpolation, direction):
     hits = rec["rgba"][:, 3] == 1.0
     assert hits.sum() > 300, "the scene should show a surface"
     assert np.all((img[:, 3] == 0.0) | (img[:, 3] == 1.0))
-    assert st["flagged_pixels"] < 0.2 * hits.size
+    # a pixel whose crossing decision lies within its margin is unconstrained: few of the surface
+    assert st["unconstrained_pixels"] <= 0.05 * hits.sum(), (st["unconstrained_pixels"], int(hits.sum()))
 
 
 def test_iso_two_surfaces_and_clip(ctx):
@@ -90,7 +91,7 @@ def test_iso_bilinear_closed_form(ctx):
         img, cnt = render(ctx, sc)
         rec = oracle.render(sc)
         st = compare(img, cnt, rec, label=f"iso bilinear sign={sign}")
-        assert st["flagged_pixels"] <= 0.2 * img.shape[0]
+        assert st["unconstrained_pixels"] <= 0.05 * img.shape[0]
         assert np.all(img[:, 3] == 1.0)
 
 
@@ -147,5 +148,6 @@ def test_iso_full_size_sampled(ctx):
     st = compare(img[px[:, 1], px[:, 0]], cnt[px[:, 1], px[:, 0]], rec, label="iso pic3 256^3 1080p sampled")
     hits = rec["rgba"][:, 3] == 1.0
     assert hits.sum() > 500, "the sample should contain surface pixels"
-    assert st["flagged_pixels"] < 0.2 * hits.size
+    # a pixel whose crossing decision lies within its margin is unconstrained: few of the surface
+    assert st["unconstrained_pixels"] <= 0.05 * hits.sum(), (st["unconstrained_pixels"], int(hits.sum()))
     assert np.all((img[..., 3] == 0.0) | (img[..., 3] == 1.0))

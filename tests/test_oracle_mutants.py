@@ -58,7 +58,8 @@ MUTANTS = [
     ("half_exponent_bias", "e - 25);", "e - 24);"),
     ("bf16_shift", "(uint32_t)b << 16;", "(uint32_t)b << 15;"),
     ("parallel_slab_open", "if (o[a] < 0.0 || o[a] > n) return 0;", "if (o[a] < 0.0) return 0;"),
-    ("exit_inclusive", "int inside = t < t1;", "int inside = t <= t1 + 0.25;"),
+    ("exit_inclusive", "const double delta = sc->delta;\n    for (int64_t k = 0;; k++) {\n        double t = scan_param(sc, t0, k);\n        int inside = t < t1;",
+     "const double delta = sc->delta;\n    for (int64_t k = 0;; k++) {\n        double t = scan_param(sc, t0, k);\n        int inside = t <= t1 + 0.25;"),
     ("iso_midpoint", "f = (src->iso - prev[s]) / (x[s] - prev[s]);", "f = 0.5;"),
     ("iso_refine_from_far_end", "double ts = t_prev + f * (t - t_prev)", "double ts = t - f * (t - t_prev)"),
     ("iso_light_swapped", "double light = 0.3 + 0.7 * cosine;", "double light = 0.7 + 0.3 * cosine;"),
@@ -70,6 +71,46 @@ MUTANTS = [
     ("encode_alpha_as_transmittance", "float transmit = 1.0f - px[3];", "float transmit = px[3];"),
     ("encode_alpha_kept_over_bg", "q[3] = 255;", "q[3] = quantize_channel(px[3]);"),
     ("iso_translucent", "px->rgba[3] = 1.0;\n            break;", "px->rgba[3] = 0.5;\n            break;"),
+    # the several-correct-results bookkeeping (decisions within their margins)
+    ("nearest_margin_x100", "fabs(p[a] - r) < P->sc->delta", "fabs(p[a] - r) < 100.0 * P->sc->delta"),
+    ("nearest_alternative_same_cell", "alt[a] = (cell[a] == (int)r) ? (int)r - 1 : (int)r;", "alt[a] = cell[a];"),
+    ("nearest_allowance_without_T", "allowance += T * worst;", "allowance += worst;"),
+    ("every_point_flagged_clip",
+     "int kind = (near_plane ? ORACLE_FLAG_CLIP : 0) | (near_exit ? ORACLE_FLAG_EXIT : 0);\n        double T",
+     "int kind = ORACLE_FLAG_CLIP | (near_exit ? ORACLE_FLAG_EXIT : 0);\n        double T"),
+    ("clip_margin_unnormalised", "if (fabs(s) < sc->delta * nn) *near_plane = 1;",
+     "if (fabs(s) < sc->delta) *near_plane = 1;"),
+    ("exit_never_flagged",
+     "int near_exit = (t1 - t < delta) && (t - t1 < delta);\n"
+     "        int kind = (near_plane ? ORACLE_FLAG_CLIP : 0) | (near_exit ? ORACLE_FLAG_EXIT : 0);\n        double T",
+     "int near_exit = 0;\n"
+     "        int kind = (near_plane ? ORACLE_FLAG_CLIP : 0) | (near_exit ? ORACLE_FLAG_EXIT : 0);\n        double T"),
+    ("kept_flag_without_T",
+     "/* the other side might drop it */\n            allowance += T * max_abs_diff",
+     "/* the other side might drop it */\n            allowance += max_abs_diff"),
+    ("count_slack_inflated",
+     "/* the other side might drop it */\n            allowance += T * max_abs_diff(E, S, (double[3]){0, 0, 0}, 0.0);\n"
+     "            flags++;\n            kinds |= kind;\n            px->count_slack++;",
+     "/* the other side might drop it */\n            allowance += T * max_abs_diff(E, S, (double[3]){0, 0, 0}, 0.0);\n"
+     "            flags++;\n            kinds |= kind;\n            px->count_slack += 2;"),
+    ("ert_margin_x100", "if (A - sc->ert_threshold < sc->ert_margin) {",
+     "if (A - sc->ert_threshold < 100.0 * sc->ert_margin) {"),
+    ("ert_before_margin_x100", "if (sc->ert_threshold - A < sc->ert_margin) {",
+     "if (sc->ert_threshold - A < 100.0 * sc->ert_margin) {"),
+    ("ert_allowance_is_A",
+     "/* the other side might go on */\n                allowance += 1.0 - A;",
+     "/* the other side might go on */\n                allowance += A;"),
+    ("iso_margin_x100", "return m + P->sc->iso_margin * (1.0 + fabs(x));",
+     "return m + 100.0 * P->sc->iso_margin * (1.0 + fabs(x));"),
+    ("iso_always_unconstrained", "    if (unconstrained) {\n        px->allowance = 2.0;",
+     "    if (1) {\n        px->allowance = 2.0;"),
+    ("iso_unconstrained_by_any_flag", "    if (unconstrained) {\n        px->allowance = 2.0;",
+     "    if (px->flags) {\n        px->allowance = 2.0;"),
+    ("iso_crossing_flag_ignored", "if (flagged_here || prev_flagged) unconstrained = 1;",
+     "if (flagged_here) unconstrained = 1;"),
+    ("iso_pending_ignored", "if (pending && sides != pending_sides) unconstrained = 1;", ""),
+    ("iso_margin_without_position", "        m += up > dn ? up : dn;\n", ""),
+    ("iso_margin_one_side", "m += up > dn ? up : dn;", "m += up;"),
 ]
 
 CHILD = r"""
