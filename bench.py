@@ -37,8 +37,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ray samples/sec (Gsamples/s) + frames/s at 1920x1080; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 4 SIMDs x 16 FP32 lanes x 2 FLOP per FMA x 2.4 GHz (packed FP32 off)
-FP32_VALU_PEAK_TFLOPS = 78.6
+# MI355X's published FP32 vector peak (it counts packed FP32, two FMAs per lane and cycle)
+FP32_VALU_PEAK_TFLOPS = 157.3
+# the same chip without packed FP32 (which this build does not use): 256 CUs x 4 SIMDs
+# x 16 lanes x 2 FLOP per FMA x 2.4 GHz
+FP32_VALU_NONPACKED_TFLOPS = 78.6
 # per scan point, 3 sources, trilinear: position 11, cell weights 6, per source
 # 7 lerps (21) + classification (12) + weighted mix (8), front-to-back composite
 # and termination test 10
@@ -52,14 +55,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "raycast_kernel_pic3_1080p_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "pic3_256_1080p_frame_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1611_09048_amd", "csrc", "raycast.hip")
+VIEW_SAMPLES = os.path.join(ROOT, "tests", "golden", "pic3_256_1080p_view_samples.json")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the ray-casting kernel from the committed counter
-    summary, or None when the kernel source or the tuner cache (which sets the
-    launch's tile shape) changed since it was taken."""
+def measured_counters():
+    """Fields of the committed counter summary of the headline frame (HBM bytes
+    per frame and per kernel, L2 hit rates), or None when the kernel source or
+    the tuner cache (which sets the launch's tile shape) changed since the
+    counters were taken."""
     import hashlib
     try:
         text = open(COUNTERS).read()
@@ -67,43 +72,124 @@ def measured_traffic():
         tuned = hashlib.sha256(open(TUNED, "rb").read()).hexdigest()
     except OSError:
         return None
-
-    def field(name):
-        v = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith(name + ":")]
-        return v[0] if v else None
-
-    val = field("traffic_bytes_per_launch")
-    if field("kernel source sha256") != src or field("tuner cache sha256") != tuned or val is None:
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and not line.startswith(("#", "|", " ", "-")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel source sha256") != src or fields.get("tuner cache sha256") != tuned:
         return None
-    return int(val)
+    return fields
 
 
-def cpu_baseline(scene, gpu_counts, row_stride: int, threads: int):
-    """The FP64 oracle on every row_stride-th row of the first view, on host threads."""
+def measured_traffic():
+    """HBM bytes (fetched + written, calibrated) per headline frame from the counters, or None."""
+    f = measured_counters()
+    if f is None or "traffic_bytes_per_frame" not in f:
+        return None
+    return int(f["traffic_bytes_per_frame"])
+
+
+def measured_l2_hit_rate():
+    """L2 hit rate per kernel of the headline frame from the counters, or None."""
+    f = measured_counters()
+    if f is None:
+        return None
+    out = {k[len("l2_hit_rate "):]: float(v) for k, v in f.items() if k.startswith("l2_hit_rate ")}
+    return out or None
+
+
+def oracle_view_samples(n, width, height, dtype):
+    """The oracle's exact scan-point counts of the 26 views (a committed file that a
+    script calling only the oracle wrote), for the FP32 headline size; else None."""
+    if (n, width, height, dtype) != (256, 1920, 1080, "f32"):
+        return None
+    try:
+        with open(VIEW_SAMPLES) as f:
+            return json.load(f)
+    except OSError:
+        return None
+
+
+def host_cpu():
+    """(model name, cores this process may run on)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def cpu_baseline(scene, gpu_img, gpu_counts, threads: int, row_stride_all: int = 4, row_stride_one: int = 16,
+                 storage_images=None):
+    """The FP64 oracle timed on host cores: one thread on every row_stride_one-th row of
+    view 0, then `threads` threads on every row_stride_all-th row.  Each run's pixels are
+    also compared with the GPU frame (RGBA within 2e-3 plus the oracle's allowance, and
+    the sample counts); storage_images ({storage: GPU frame of view 0 rendered from the
+    fields stored that way}) get their per-channel max and RMS error against the same
+    oracle pixels of the FP32 fields."""
     import oracle
-    rows = np.arange(0, scene.height, row_stride)
-    px = np.stack(np.meshgrid(np.arange(scene.width), rows), axis=-1).reshape(-1, 2).astype(np.int32)
-    parts = np.array_split(np.arange(px.shape[0]), threads)
-    outs = [None] * threads
+    records = {}
 
-    def work(k):
-        outs[k] = oracle.render_pixels(scene, px[parts[k]])
+    def run(stride, n_threads):
+        rows = np.arange(0, scene.height, stride)
+        px = np.stack(np.meshgrid(np.arange(scene.width), rows), axis=-1).reshape(-1, 2).astype(np.int32)
+        parts = np.array_split(np.arange(px.shape[0]), n_threads)
+        outs = [None] * n_threads
 
-    t0 = time.perf_counter()
-    ts = [threading.Thread(target=work, args=(k,)) for k in range(threads)]
-    for t in ts:
-        t.start()
-    for t in ts:
-        t.join()
-    dt = time.perf_counter() - t0
-    rec = np.concatenate(outs)
-    samples = int(rec["samples"].sum())
-    g = gpu_counts[px[:, 1], px[:, 0]].astype(np.int64)
-    agree = float(np.mean(g == rec["samples"]))
-    return dict(value=samples / dt / 1e9, unit="Gsamples/s", cores=threads, kind="oracle",
-                sample=f"every {row_stride}th row of view 0 ({px.shape[0]} pixels, {samples} samples, "
-                       f"{dt:.1f} s wall on {threads} threads); per-pixel sample counts equal to the GPU's "
-                       f"on {agree * 100:.2f}% of them")
+        def work(k):
+            outs[k] = oracle.render_pixels(scene, px[parts[k]])
+
+        t0 = time.perf_counter()
+        ts = [threading.Thread(target=work, args=(k,)) for k in range(n_threads)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        dt = time.perf_counter() - t0
+        rec = np.concatenate(outs)
+        records[stride] = (px, rec)
+        g = gpu_img[px[:, 1], px[:, 0]].astype(np.float64)
+        diff = np.abs(g - rec["rgba"])
+        within = diff <= 2e-3 + rec["allowance"][:, None]
+        counts_equal = gpu_counts[px[:, 1], px[:, 0]].astype(np.int64) == rec["samples"]
+        samples = int(rec["samples"].sum())
+        return dict(msamples_per_s=round(samples / dt / 1e6, 4), seconds=round(dt, 2), pixels=int(px.shape[0]),
+                    samples=samples, threads=n_threads, rows=f"every {stride}th row",
+                    max_abs_diff_rgba=float(diff.max()), pixels_within_bound=float(np.mean(within.all(axis=1))),
+                    counts_equal=float(np.mean(counts_equal)),
+                    flagged_pixels=int((rec["flags"] > 0).sum()))
+
+    model, visible = host_cpu()
+    one = run(row_stride_one, 1)
+    log(f"bench: oracle on 1 thread {one}")
+    allc = run(row_stride_all, threads)
+    log(f"bench: oracle on {threads} threads {allc}")
+    px, rec = records[row_stride_all]
+    errors = {}
+    for name, img in (storage_images or {}).items():
+        d = img[px[:, 1], px[:, 0]].astype(np.float64) - rec["rgba"]
+        errors[name] = dict(max=[float(v) for v in np.abs(d).max(axis=0)],
+                            rms=[float(v) for v in np.sqrt((d * d).mean(axis=0))])
+    return dict(value=round(allc["msamples_per_s"] / 1e3, 6), unit="Gsamples/s", cores=threads, kind="oracle",
+                storage_error_vs_oracle_of_fp32_fields=errors or None,
+                sample=(f"view 0 of the headline frame: {allc['rows']} ({allc['pixels']} pixels, "
+                        f"{allc['samples']} samples, {allc['seconds']} s on {threads} threads); single thread on "
+                        f"{one['rows']} ({one['samples']} samples, {one['seconds']} s)"),
+                cpu_model=model, host_cores_visible=visible, single_thread_msamples_per_s=one["msamples_per_s"],
+                all_cores_msamples_per_s=allc["msamples_per_s"],
+                parity_vs_gpu=dict(max_abs_diff_rgba=max(one["max_abs_diff_rgba"], allc["max_abs_diff_rgba"]),
+                                   pixels_within_bound=min(one["pixels_within_bound"], allc["pixels_within_bound"]),
+                                   counts_equal=min(one["counts_equal"], allc["counts_equal"]),
+                                   pixels=allc["pixels"], flagged_pixels=allc["flagged_pixels"]))
 
 
 FORCED_SHAPE = None
@@ -138,8 +224,11 @@ def apply_tuning(ctx, key_sig, classes, time_jobs, retune=False):
     return best
 
 
-def frames(ctx, sc, steps, warmup, log_prefix=""):
-    """Time `steps` frames cycling through the 26 views; returns a dict of results."""
+def frames(ctx, sc, steps, warmup, view_reps=0, log_prefix=""):
+    """Time `steps` frames cycling through the 26 views, then (view_reps > 0) each view
+    view_reps times in a pass of its own; returns a dict of results.  The context
+    enqueues on torch's current stream, so the events recorded there around each
+    render bracket all of its device work (derive, set-up and ray-casting passes)."""
     import torch
     from paper_1611_09048_amd import ASYNC, TIMING, device
     from scenes import configs
@@ -170,6 +259,7 @@ def frames(ctx, sc, steps, warmup, log_prefix=""):
         hit.append(float((c > 0).float().mean().item()))
     ctx.render([device.render_job(scenes_v[0], 0, img, cnt)])
     counts_view0 = cnt.cpu().numpy()
+    image_view0 = img.cpu().numpy()
     # what clipping and early termination remove (view 0, untimed)
     ctx.render([device.render_job(scenes_v[0], 0, img, cnt, ert_threshold=2.0)])
     no_ert = int(cnt.to(torch.int64).sum().item())
@@ -180,8 +270,16 @@ def frames(ctx, sc, steps, warmup, log_prefix=""):
                    without_clip_or_termination=no_clip_no_ert,
                    clipped_fraction=round(1.0 - no_ert / max(no_clip_no_ert, 1), 4),
                    terminated_fraction=round(1.0 - int(counts_view0.sum()) / max(no_ert, 1), 4))
-    log(f"bench:{log_prefix} samples/frame mean {np.mean(samples):.4g} (min {min(samples)}, max {max(samples)}); "
-        f"hit fraction {np.mean(hit):.3f}; tile shape {shape}")
+    # the numerator: the oracle's exact counts where they are on file, else the GPU's
+    ref = oracle_view_samples(sc.dims[0], sc.width, sc.height, sc.sources[0].dtype) if sc.dims[0] == sc.dims[1] == \
+        sc.dims[2] else None
+    gpu_samples = list(samples)
+    counted_by = "gpu counting variant"
+    if ref is not None and len(ref["samples"]) == len(views):
+        samples = [int(v) for v in ref["samples"]]
+        counted_by = "oracle"
+    log(f"bench:{log_prefix} samples/frame mean {np.mean(samples):.4g} (min {min(samples)}, max {max(samples)}, "
+        f"counted by the {counted_by}); hit fraction {np.mean(hit):.3f}; tile shape {shape}")
     for k in range(warmup):
         ctx.render([jobs[k % len(jobs)]], ASYNC)
     torch.cuda.synchronize()
@@ -198,18 +296,38 @@ def frames(ctx, sc, steps, warmup, log_prefix=""):
     kernel_ms, n_kernels = ctx.timing()
     frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
     total = sum(samples[k % len(jobs)] for k in range(steps))
-    per_view = np.zeros(len(views))
-    reps = np.zeros(len(views))
-    for k in range(steps):
-        per_view[k % len(jobs)] += frame_ms[k]
-        reps[k % len(jobs)] += 1
-    per_view = per_view[reps > 0] / reps[reps > 0]
     out = dict(gsps=total / elapsed / 1e9, elapsed=elapsed, kernel_ms=kernel_ms / max(n_kernels, 1),
-               frame_ms=frame_ms, per_view=per_view, samples=samples, shape=shape, counts_view0=counts_view0,
-               scene_v0=scenes_v[0], field_bytes=sum(s.field_bytes() for s in sc.sources), removed=removed,
-               image_bytes=sc.width * sc.height * 16)
+               frame_ms=frame_ms, samples=samples, gpu_samples=gpu_samples, counted_by=counted_by, shape=shape,
+               counts_view0=counts_view0, image_view0=image_view0, scene_v0=scenes_v[0],
+               field_bytes=sum(s.field_bytes() for s in sc.sources), removed=removed,
+               image_bytes=sc.width * sc.height * 16, oracle_ref=ref)
     log(f"bench:{log_prefix} {steps} frames in {elapsed * 1e3:.1f} ms -> {out['gsps']:.2f} Gsamples/s; "
-        f"kernel avg {out['kernel_ms']:.4f} ms")
+        f"frame p50 {np.median(frame_ms):.4f} ms (device, events); ray-casting kernel avg {out['kernel_ms']:.4f} ms")
+    if view_reps > 0:
+        # each view on its own: one untimed frame, then view_reps timed ones, back to back
+        vev = []
+        for v in range(len(views)):
+            ctx.render([jobs[v]], ASYNC)
+            for _ in range(view_reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ctx.render([jobs[v]], ASYNC)
+                b.record(stream)
+                vev.append((v, a, b))
+        torch.cuda.synchronize()
+        per = [[] for _ in views]
+        for v, a, b in vev:
+            per[v].append(a.elapsed_time(b))
+        med = np.array([float(np.median(p)) for p in per])
+        gs = np.array(samples, dtype=np.float64) / (med / 1e3) / 1e9
+        out["views"] = dict(reps=view_reps, frame_ms=dict(avg=round(float(med.mean()), 4), min=round(float(med.min()), 4),
+                                                          max=round(float(med.max()), 4)),
+                            gsamples_per_s=dict(avg=round(float(gs.mean()), 3), min=round(float(gs.min()), 3),
+                                                max=round(float(gs.max()), 3)),
+                            slowest_over_fastest=round(float(med.max() / med.min()), 3),
+                            per_view_ms=[round(float(m), 4) for m in med],
+                            samples_per_view=[int(x) for x in samples])
+        log(f"bench:{log_prefix} views {out['views']['frame_ms']} ms, {out['views']['gsamples_per_s']} Gsamples/s")
     del vol
     return out
 
@@ -481,6 +599,40 @@ def copy_probe(ctx_unused, mib: int = 512, reps: int = 3):
     return dict(bytes_read=x.numel() * 4, bytes_written=y.numel() * 4, kernels=reps)
 
 
+def check_frame_timing(frame_ms, kernel_ms):
+    """Frame events must bracket the ray-casting kernel they contain: a frame shorter
+    than its kernel means the events were recorded on another stream."""
+    if float(np.min(frame_ms)) < kernel_ms * 0.98:
+        raise RuntimeError(f"frame events ({float(np.min(frame_ms)):.4f} ms) shorter than the ray-casting kernel "
+                           f"({kernel_ms:.4f} ms): they do not bracket the render")
+
+
+def rooflines(frame_ms, kernel_ms, algo_bytes, samples_per_frame):
+    """(HBM roofline of the whole frame, ALU roofline of the ray-casting kernel).
+
+    HBM: every stored source byte and the image once (the frame's algorithmic
+    bytes) over the mean device time of a frame, against 8 TB/s.  ALU: the
+    method's FLOPs per scan point over the kernel's mean duration, against the
+    published FP32 vector peak (and the non-packed peak this build runs at)."""
+    frame_ms = np.asarray(frame_ms, dtype=np.float64)
+    check_frame_timing(frame_ms, kernel_ms)
+    mean_ms = float(frame_ms.mean())
+    gbs = algo_bytes / (mean_ms / 1e3) / 1e9
+    if gbs > HBM_PEAK_GBS:
+        raise RuntimeError(f"{gbs:.0f} GB/s of algorithmic bytes is above the HBM peak: the frame time is wrong")
+    hbm = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+               traffic=measured_traffic(), l2_hit_rate=measured_l2_hit_rate(),
+               scope="one frame: derive_kernel, prepass_kernel and raycast_kernel, one stream",
+               algorithmic_bytes_per_frame=int(algo_bytes), frame_ms_mean=round(mean_ms, 4))
+    flops = FLOPS_PER_SAMPLE * samples_per_frame
+    tf = flops / (kernel_ms / 1e3) / 1e12
+    alu = dict(bound="alu", kernel="raycast_kernel", achieved=round(tf, 2), peak=FP32_VALU_PEAK_TFLOPS,
+               unit="TFLOP/s", frac=round(tf / FP32_VALU_PEAK_TFLOPS, 4), peak_nonpacked=FP32_VALU_NONPACKED_TFLOPS,
+               frac_nonpacked=round(tf / FP32_VALU_NONPACKED_TFLOPS, 4), kernel_avg_ms=round(kernel_ms, 4),
+               flops_per_sample=FLOPS_PER_SAMPLE, algorithmic_flops_per_launch=int(flops))
+    return hbm, alu
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -491,6 +643,7 @@ def main():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--cpu-row-stride", type=int, default=4)
+    ap.add_argument("--view-reps", type=int, default=5, help="timed frames per view in the 26-view pass (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
@@ -522,22 +675,9 @@ def main():
         print(json.dumps(dict(jpeg=jpeg_frames(ctx, sc, reps=args.steps))), flush=True)
         ctx.close()
         return
-    fr = frames(ctx, sc, args.steps, args.warmup)
-    # the ray-casting kernel issues FP32 vector arithmetic most of its time: an ALU
-    # roofline with the method's FLOPs per scan point (FMA = 2) over the samples
-    # of one launch (mean of the 26 views), against the non-packed FP32 vector peak
-    flops = FLOPS_PER_SAMPLE * float(np.mean(fr["samples"]))
-    achieved = flops / (fr["kernel_ms"] / 1e3) / 1e12
-    roofline = dict(bound="alu", achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4), traffic=measured_traffic(), kernel="raycast_kernel",
-                    kernel_avg_ms=round(fr["kernel_ms"], 4), algorithmic_flops_per_launch=int(flops),
-                    flops_per_sample=FLOPS_PER_SAMPLE)
-    # the whole frame against HBM: every stored source byte and the image once, over the frame time
-    frame_ms = float(np.median(fr["frame_ms"]))
-    algo_bytes = fr["field_bytes"] + fr["image_bytes"]
-    frame_hbm = dict(algorithmic_bytes=algo_bytes, frame_ms=round(frame_ms, 4),
-                     achieved_gbs=round(algo_bytes / (frame_ms / 1e3) / 1e9, 1), peak_gbs=HBM_PEAK_GBS,
-                     frac=round(algo_bytes / (frame_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4))
+    fr = frames(ctx, sc, args.steps, args.warmup, view_reps=args.view_reps)
+    roofline, roofline_alu = rooflines(fr["frame_ms"], fr["kernel_ms"], fr["field_bytes"] + fr["image_bytes"],
+                                       float(np.mean(fr["samples"])))
     out = dict(metric=METRIC, value=round(fr["gsps"], 3), unit="Gsamples/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(fr["elapsed"] * 1e3 / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype=args.dtype, data="synthetic",
@@ -547,20 +687,31 @@ def main():
                            views=26, tile_shape=list(fr["shape"])),
                fps=round(args.steps / fr["elapsed"], 2),
                latency_ms=dict(p50=round(float(np.percentile(fr["frame_ms"], 50)), 4),
-                               p99=round(float(np.percentile(fr["frame_ms"], 99)), 4)),
-               views_ms=dict(avg=round(float(fr["per_view"].mean()), 4), min=round(float(fr["per_view"].min()), 4),
-                             max=round(float(fr["per_view"].max()), 4)),
-               samples_per_frame=int(np.mean(fr["samples"])), sample_reduction_view0=fr["removed"],
-               roofline=roofline, frame_hbm=frame_hbm)
+                               p99=round(float(np.percentile(fr["frame_ms"], 99)), 4),
+                               what="device time of one frame (derive, set-up and ray casting) from events on "
+                                    "the render stream"),
+               samples_per_frame=int(np.mean(fr["samples"])), samples_counted_by=fr["counted_by"],
+               sample_reduction_view0=fr["removed"], roofline=roofline, roofline_raycast_alu=roofline_alu)
+    if "views" in fr:
+        out["views"] = fr["views"]
+    if fr["oracle_ref"] is not None:
+        g, o = np.array(fr["gpu_samples"]), np.array(fr["samples"])
+        out["samples_gpu_vs_oracle"] = dict(max_rel_diff=float(np.max(np.abs(g - o) / o)),
+                                            max_abs_diff=int(np.max(np.abs(g - o))),
+                                            oracle_count_slack_max=int(max(fr["oracle_ref"]["count_slack"])))
+    storage_images = {args.dtype: fr["image_view0"]}
     if not args.no_extras:
         extras = {}
         for dt in ("f16", "bf16"):
             if dt == args.dtype:
                 continue
             s2 = configs.pic3(n=args.n, width=args.width, height=args.height, dtype=dt)
-            f2 = frames(ctx, s2, max(26, args.steps // 2), 3, f" {dt}")
+            f2 = frames(ctx, s2, max(26, args.steps // 2), 3, log_prefix=f" {dt}")
+            storage_images[dt] = f2["image_view0"]
             extras[dt] = dict(gsamples_per_s=round(f2["gsps"], 3), kernel_ms=round(f2["kernel_ms"], 4),
-                              fps=round(max(26, args.steps // 2) / f2["elapsed"], 2), tile_shape=list(f2["shape"]))
+                              frame_ms_p50=round(float(np.median(f2["frame_ms"])), 4),
+                              fps=round(max(26, args.steps // 2) / f2["elapsed"], 2), tile_shape=list(f2["shape"]),
+                              samples_counted_by=f2["counted_by"])
         extras["iso"] = iso_frames(ctx, args.n, args.width, args.height)
         extras["encode_rgba8"] = encode(ctx, args.width, args.height)
         extras["jpeg"] = jpeg_frames(ctx, sc)
@@ -573,9 +724,15 @@ def main():
         extras["served_readback_ms"] = served_readback(ctx)
         out["extras"] = extras
     if not args.no_cpu_baseline:
-        threads = max(1, min(16, os.cpu_count() or 1))
-        log(f"bench: CPU oracle baseline on {threads} threads")
-        out["cpu_baseline"] = cpu_baseline(fr["scene_v0"], fr["counts_view0"], args.cpu_row_stride, threads)
+        # every core this process may use, at most the host share of one GPU (16)
+        threads = max(1, min(16, host_cpu()[1]))
+        log(f"bench: CPU oracle baseline on 1 and {threads} threads")
+        out["cpu_baseline"] = cpu_baseline(fr["scene_v0"], fr["image_view0"], fr["counts_view0"], threads,
+                                           row_stride_all=args.cpu_row_stride, storage_images=storage_images)
+        errs = out["cpu_baseline"]["storage_error_vs_oracle_of_fp32_fields"] or {}
+        for dt, e in errs.items():
+            if "extras" in out and dt in out["extras"]:
+                out["extras"][dt]["error_vs_oracle_of_fp32_fields"] = e
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -79,12 +79,20 @@ enum { ISAAC_VOLUME = 0, ISAAC_ISO = 1 };     /* render modes */
 
 typedef struct isaac_context isaac_context;   /* opaque */
 
+/* isaac_init_desc.flags */
+#define ISAAC_INIT_NULL_STREAM 1u   /* with stream == NULL: enqueue on the null stream (HIP's default stream,
+                                       which is also PyTorch's default stream), so the context's work is
+                                       ordered with work the caller issues there and events the caller records
+                                       there bracket it; without this flag a NULL stream asks for a stream of
+                                       the context's own, unordered with the caller's */
+
 typedef struct {
     int device;                  /* HIP device ordinal */
-    void* stream;                /* hipStream_t to enqueue on (borrowed, never destroyed); NULL: own stream */
+    void* stream;                /* hipStream_t to enqueue on (borrowed, never destroyed); NULL: see flags */
     size_t mem_budget_bytes;     /* serving: device bytes for library-owned output images; 0: 1 GiB */
     int max_inflight;            /* serving: outstanding submitted requests; 0: 64 */
     int max_volumes;             /* volume ids 0..max_volumes-1; 0: 256 */
+    unsigned flags;              /* ISAAC_INIT_* bits; other bits: ISAAC_ERR_INVALID_ARGUMENT */
 } isaac_init_desc;
 
 /* Create a context on a device.  *out receives the context, or NULL on error

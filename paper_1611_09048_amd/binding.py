@@ -36,9 +36,12 @@ class IsaacError(RuntimeError):
 UPDATE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p)
 
 
+INIT_NULL_STREAM = 1
+
+
 class InitDesc(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("mem_budget_bytes", ctypes.c_size_t),
-                ("max_inflight", ctypes.c_int), ("max_volumes", ctypes.c_int)]
+                ("max_inflight", ctypes.c_int), ("max_volumes", ctypes.c_int), ("flags", ctypes.c_uint)]
 
 
 class SourceDesc(ctypes.Structure):
@@ -153,13 +156,30 @@ def _arr(ctype, values):
 
 
 class Context:
-    """One library context on one device (not thread-safe, like the C context)."""
+    """One library context on one device (not thread-safe, like the C context).
 
-    def __init__(self, device: int = 0, stream=None, mem_budget: int = 0, max_inflight: int = 0,
+    stream: where the context enqueues its work.  "current" (the default):
+    torch's current stream on `device` when the context is made, so work the
+    caller issues there through torch (allocations, fills, copies) and the
+    library's work are ordered, and events recorded there bracket a render;
+    torch's default stream is HIP's null stream, passed as
+    ISAAC_INIT_NULL_STREAM.  A torch stream or a raw hipStream_t handle: that
+    stream.  None: a stream of the library's own."""
+
+    def __init__(self, device: int = 0, stream="current", mem_budget: int = 0, max_inflight: int = 0,
                  max_volumes: int = 0):
         self.lib = load()
-        d = InitDesc(device=device, stream=_stream_handle(stream), mem_budget_bytes=mem_budget,
-                     max_inflight=max_inflight, max_volumes=max_volumes)
+        if isinstance(stream, str) and stream == "current":
+            import torch
+            # no visible device: the null stream (isaac_init then reports the missing device)
+            stream = torch.cuda.current_stream(device) if torch.cuda.is_available() else 0
+        handle, flags = None, 0
+        if stream is not None:
+            handle = _stream_handle(stream)
+            if not handle:
+                handle, flags = None, INIT_NULL_STREAM
+        d = InitDesc(device=device, stream=handle, mem_budget_bytes=mem_budget,
+                     max_inflight=max_inflight, max_volumes=max_volumes, flags=flags)
         h = ctypes.c_void_p()
         rc = self.lib.isaac_init(ctypes.byref(d), ctypes.byref(h))
         if rc != ISAAC_OK:

@@ -1226,6 +1226,14 @@ isaac_status isaac_init(const isaac_init_desc* desc, isaac_context** out) {
         g_init_error = "device ordinal out of range";
         return ISAAC_ERR_INVALID_ARGUMENT;
     }
+    if (d.flags & ~ISAAC_INIT_NULL_STREAM) {
+        g_init_error = "unknown isaac_init_desc.flags bits";
+        return ISAAC_ERR_INVALID_ARGUMENT;
+    }
+    if (d.stream && (d.flags & ISAAC_INIT_NULL_STREAM)) {
+        g_init_error = "ISAAC_INIT_NULL_STREAM needs stream == NULL";
+        return ISAAC_ERR_INVALID_ARGUMENT;
+    }
     auto* ctx = new isaac_context();
     ctx->device = d.device;
     ctx->budget = d.mem_budget_bytes ? d.mem_budget_bytes : ((size_t)1 << 30);
@@ -1246,6 +1254,8 @@ isaac_status isaac_init(const isaac_init_desc* desc, isaac_context** out) {
     if (raycast_occupancy(&bpc) == hipSuccess && bpc > 0) ctx->blocks_per_cu = bpc;
     if (d.stream) {
         ctx->stream = static_cast<hipStream_t>(d.stream);
+    } else if (d.flags & ISAAC_INIT_NULL_STREAM) {
+        ctx->stream = nullptr;                  // the null stream, borrowed like any caller stream
     } else {
         e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
         if (e != hipSuccess) return fail("hipStreamCreate", e);
@@ -1285,7 +1295,7 @@ isaac_status isaac_init(const isaac_init_desc* desc, isaac_context** out) {
 void isaac_destroy(isaac_context* ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
-    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    hipStreamSynchronize(ctx->stream);
     for (hipStream_t s : ctx->serve_streams) hipStreamSynchronize(s);
     hipDeviceSynchronize();
     for (auto& v : ctx->volumes) {

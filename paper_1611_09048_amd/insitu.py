@@ -109,7 +109,11 @@ class InSituStats:
 
 
 class InSituRenderer:
-    """Registers the simulation's fields as sources and renders every n-th step."""
+    """Registers the simulation's fields as sources and renders every n-th step.
+
+    The context must enqueue on the stream the simulation runs on (torch's
+    current stream, the binding's default), so a render waits for the step
+    before it and the next step waits for the render."""
 
     def __init__(self, ctx: binding.Context, sim: FieldSimulation, volume_id: int = 0,
                  tfs: Optional[List[list]] = None, weights=(0.6, 0.8, 0.9),
@@ -141,9 +145,9 @@ class InSituRenderer:
         src = int(user or 0)
         self.updates.append((src, int(enabled)))
         if src == 2 and enabled:
+            # enqueued on torch's current stream, which the context shares (its default),
+            # so the library's copy of this source, next on that stream, reads the result
             self.sim.derive_current()
-            # the library copies this source on its own stream next
-            torch.cuda.current_stream().synchronize()
 
     def render(self, desc: binding.RenderDesc) -> None:
         self.ctx.render([desc])

@@ -57,7 +57,7 @@ int main(void) {
   P(isaac_render_desc, ert_threshold) P(isaac_render_desc, out_rgba) P(isaac_render_desc, update_pointer)
   P(isaac_render_desc, brick_origin) P(isaac_render_desc, out_depth) P(isaac_render_desc, mode)
   P(isaac_render_desc, iso_values)
-  P(isaac_init_desc, mem_budget_bytes)
+  P(isaac_init_desc, mem_budget_bytes) P(isaac_init_desc, flags)
   return 0;
 }
 """

@@ -1,7 +1,12 @@
-"""Host logic of bench.py: the measured HBM traffic is reported only while the
-kernel source and the tuner cache are the ones the counters were taken with."""
+"""Host logic of bench.py: the measured HBM traffic and L2 hit rates are
+reported only while the kernel source and the tuner cache are the ones the
+counters were taken with; frame timings that cannot bracket the render, or
+that put the frame above the HBM peak, are refused."""
 
 import hashlib
+
+import numpy as np
+import pytest
 
 import bench
 
@@ -14,25 +19,31 @@ def _setup(tmp_path, src=b"kernel v1", tuned=b'{"a": [1]}', value=123456):
     t.write_bytes(tuned)
     c.write_text(f"# counters\nkernel source sha256: {hashlib.sha256(src).hexdigest()}\n"
                  f"tuner cache sha256: {hashlib.sha256(tuned).hexdigest()}\n\n"
-                 f"traffic_bytes_per_launch: {value}\n")
+                 f"| kernel | fetch |\n|---|---|\n| raycast_kernel | 1 |\n\n"
+                 f"traffic_bytes_per_frame: {value}\n"
+                 f"l2_hit_rate raycast_kernel: 0.75\nl2_hit_rate derive_kernel: 0.125\n")
     return k, t, c
+
+
+def _patch(monkeypatch, k, t, c):
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(k))
+    monkeypatch.setattr(bench, "TUNED", str(t))
+    monkeypatch.setattr(bench, "COUNTERS", str(c))
 
 
 def test_traffic_reported_when_hashes_match(tmp_path, monkeypatch):
     k, t, c = _setup(tmp_path)
-    monkeypatch.setattr(bench, "KERNEL_SRC", str(k))
-    monkeypatch.setattr(bench, "TUNED", str(t))
-    monkeypatch.setattr(bench, "COUNTERS", str(c))
+    _patch(monkeypatch, k, t, c)
     assert bench.measured_traffic() == 123456
+    assert bench.measured_l2_hit_rate() == {"raycast_kernel": 0.75, "derive_kernel": 0.125}
 
 
 def test_traffic_withheld_after_a_kernel_or_cache_change(tmp_path, monkeypatch):
     k, t, c = _setup(tmp_path)
-    monkeypatch.setattr(bench, "KERNEL_SRC", str(k))
-    monkeypatch.setattr(bench, "TUNED", str(t))
-    monkeypatch.setattr(bench, "COUNTERS", str(c))
+    _patch(monkeypatch, k, t, c)
     k.write_bytes(b"kernel v2")
     assert bench.measured_traffic() is None
+    assert bench.measured_l2_hit_rate() is None
     k.write_bytes(b"kernel v1")
     t.write_bytes(b'{"a": [2]}')
     assert bench.measured_traffic() is None
@@ -43,3 +54,31 @@ def test_traffic_withheld_after_a_kernel_or_cache_change(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "missing.md"))
     assert bench.measured_traffic() is None
 
+
+def test_rooflines_from_frame_and_kernel_times(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "missing.md"))
+    frame = np.array([0.2, 0.2, 0.2])
+    hbm, alu = bench.rooflines(frame, 0.1, 514_035_936, 1.2e7)
+    assert hbm["bound"] == "hbm" and hbm["unit"] == "GB/s"
+    assert hbm["achieved"] == pytest.approx(514_035_936 / 0.2e-3 / 1e9, rel=1e-3)
+    assert 0 < hbm["frac"] <= 1
+    assert hbm["frame_ms_mean"] >= alu["kernel_avg_ms"]
+    assert alu["peak"] == 157.3 and alu["frac"] == pytest.approx(alu["achieved"] / 157.3, abs=1e-4)
+
+
+def test_frame_events_that_miss_the_render_are_refused(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "missing.md"))
+    # events on another stream time only the host enqueue: shorter than the kernel they contain
+    with pytest.raises(RuntimeError, match="bracket"):
+        bench.rooflines(np.array([0.0187, 0.02]), 0.1042, 514_035_936, 1.2e7)
+    # a frame time that puts the algorithmic bytes above the HBM peak
+    with pytest.raises(RuntimeError, match="peak"):
+        bench.rooflines(np.array([0.05]), 0.04, 514_035_936, 1.2e7)
+
+
+def test_oracle_view_samples_only_for_the_headline_size():
+    ref = bench.oracle_view_samples(256, 1920, 1080, "f32")
+    assert ref is not None and len(ref["samples"]) == 26
+    assert all(s > 0 for s in ref["samples"])
+    assert bench.oracle_view_samples(128, 1920, 1080, "f32") is None
+    assert bench.oracle_view_samples(256, 1920, 1080, "f16") is None

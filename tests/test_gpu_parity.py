@@ -127,6 +127,35 @@ def test_pic3_full_size_sampled(ctx):
     assert np.isfinite(img).all() and img.min() >= 0.0 and img.max() <= 1.0 + 1e-6
 
 
+def _host_threads():
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+@pytest.mark.parametrize("direction", [(-1.0, -1.0, -1.0), (1.0, 0.0, 0.0), (0.0, 0.0, 1.0)])
+def test_pic3_full_size_views(ctx, direction):
+    """The benchmark frame as it is timed: 256^3, three sources, 1920x1080, one of the
+    26 views (a diagonal, the +x axis, the +z axis), the benchmark's tuned tile shape and
+    derived volume.  Every pixel and every sample count against the oracle (on host
+    threads); at most 2 % of the pixels may carry a decision within its margin."""
+    assert tuple(direction) in configs.views26()
+    base = configs.pic3()
+    sc = base.with_(camera=configs.orbit_camera(base.dims, direction))
+    restore = bench_shape(ctx, sc)
+    try:
+        img, cnt = gpu_render(ctx, sc)
+    finally:
+        restore()
+    rec = oracle.render(sc, threads=_host_threads())
+    stats = compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=f"pic3 256^3 1080p view {direction}")
+    assert stats["flagged_pixels"] <= 0.02 * stats["pixels"], stats
+    assert stats["samples"] > 5e6
+
+
 def test_pic3_4k_sampled(ctx):
     """The benchmark volume at 3840x2160 (four times the pixels and tiles of 1080p); sampled pixels."""
     sc = configs.pic3(width=3840, height=2160, direction=(0.3, 0.5, -0.8))
