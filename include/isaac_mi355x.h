@@ -219,6 +219,31 @@ typedef struct {
  * calls (isaac_submit*) never derive. */
 isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the render of
+ * isaac_render, with the same images bit for bit, that calls no hipMalloc,
+ * hipFree or other allocating routine.
+ *   - The set-up pass writes its ray records (40 bytes per pixel of each job's
+ *     screen rectangle, the projected box) into a static device array of
+ *     ISAAC_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ *     on until the process ends.  A call whose jobs' rectangles together need
+ *     more is refused with ISAAC_ERR_INVALID_ARGUMENT before anything runs (at
+ *     most 838860 rectangle pixels: e.g. any 1024x768 job, or a 1920x1080 job
+ *     whose volume covers up to 40 % of the screen).
+ *   - No derived volume is built: a frozen volume's derived values are read
+ *     (isaac_freeze_volume), other volumes are read in place, as with
+ *     ISAAC_DIRECT.  Non-persistent sources are copied into the buffers
+ *     isaac_set_sources allocated.
+ *   - Batches are launched directly (no hipGraph); no pooled schedule.
+ *   - flags: ISAAC_ASYNC, ISAAC_NO_GRAPH, ISAAC_DIRECT; any other bit
+ *     (ISAAC_TIMING, ISAAC_DERIVE) is ISAAC_ERR_INVALID_ARGUMENT.
+ * Every call on a device shares that device's array, whose contents the next
+ * call overwrites: calls that overlap on one device (on other streams or from
+ * other contexts) race and must be ordered by the caller; calls on one
+ * context's stream are ordered already. */
+#define ISAAC_NOALLOC_SCRATCH_BYTES (32u << 20)
+isaac_status isaac_render_noalloc(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags);
+
 /* Sort-last compositing (Sec. 3.1, Fig. "whole concept"): per pixel, order the
  * n_layers partial images by their depth images (out_depth of the brick
  * renders) and combine them front to back:

@@ -74,7 +74,8 @@ class RenderDesc(ctypes.Structure):
 
 
 EXPORTS = ["isaac_init", "isaac_destroy", "isaac_last_error", "isaac_init_error", "isaac_set_sources",
-           "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_composite", "isaac_encode_rgba8",
+           "isaac_set_transfer", "isaac_release_transfer", "isaac_render", "isaac_render_noalloc",
+           "isaac_composite", "isaac_encode_rgba8",
            "isaac_timing", "isaac_set_tile_shape", "isaac_get_tile_shape", "isaac_submit", "isaac_submit_batch",
            "isaac_poll", "isaac_release", "isaac_read_image", "isaac_read_image_rgba8", "isaac_encode_jpeg", "isaac_read_image_jpeg", "isaac_freeze_volume", "isaac_serving_usage",
            "isaac_check_functor_chain", "isaac_version"]
@@ -106,6 +107,7 @@ def load(path: Optional[str] = None):
                                        ctypes.POINTER(ctypes.c_int32)]
     lib.isaac_release_transfer.argtypes = [c_ctx, ctypes.c_int32]
     lib.isaac_render.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.c_int, ctypes.c_uint]
+    lib.isaac_render_noalloc.argtypes = [c_ctx, ctypes.POINTER(RenderDesc), ctypes.c_int, ctypes.c_uint]
     lib.isaac_timing.argtypes = [c_ctx, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.isaac_composite.argtypes = [c_ctx, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint]
@@ -230,6 +232,11 @@ class Context:
     def render(self, jobs: Sequence[RenderDesc], flags: int = 0):
         arr = (RenderDesc * len(jobs))(*jobs)
         self._check(self.lib.isaac_render(self.h, arr, len(jobs), flags))
+
+    def render_noalloc(self, jobs: Sequence[RenderDesc], flags: int = 0):
+        """isaac_render_noalloc: the same images, no device allocation (static scratch)."""
+        arr = (RenderDesc * len(jobs))(*jobs)
+        self._check(self.lib.isaac_render_noalloc(self.h, arr, len(jobs), flags))
 
     def composite(self, rgba_ptrs, depth_ptrs, width: int, height: int, out_ptr: int, flags: int = 0):
         """Sort-last over-compositing of partial images (device pointers) into out_ptr."""

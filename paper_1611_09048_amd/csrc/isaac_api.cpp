@@ -245,6 +245,7 @@ struct RingSlot {
 struct Pending {
     uint64_t seq;
     hipEvent_t ev;
+    bool pooled = true;             // false: a staging-ring event, not returned to the event pool
 };
 
 struct Ticket {
@@ -298,6 +299,7 @@ struct isaac_context {
     void* pool_rays = nullptr;         // compacted rays of the pooled schedule
     size_t pool_bytes = 0;
     int* pool_counters = nullptr;      // [appended rays, handed-out rays]
+    void* noalloc_scratch = nullptr;   // this device's static scratch (ray records of isaac_render_noalloc)
     TileShape shapes[16];
     std::string last_error;
     bool sticky = false;
@@ -354,7 +356,7 @@ void update_completed(isaac_context* ctx) {
         Pending& p = ctx->pending.front();
         if (hipEventQuery(p.ev) != hipSuccess) break;
         ctx->completed = p.seq;
-        put_event(ctx, p.ev);
+        if (p.pooled) put_event(ctx, p.ev);
         ctx->pending.pop_front();
     }
     for (size_t i = 0; i < ctx->tf_slots.size(); ++i) {
@@ -806,8 +808,11 @@ bool ensure_pool(isaac_context* ctx, size_t bytes, hipStream_t stream) {
     return true;
 }
 
+// noalloc: the call may not allocate: the set-up pass writes its ray records
+// into the context device's static scratch (the caller checked they fit), no
+// pooled schedule, no hipGraph, and the staging ring's event marks completion.
 isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, const std::vector<DevJob>& djs,
-                          int max_src, unsigned flags, hipStream_t stream, bool allow_pool) {
+                          int max_src, unsigned flags, hipStream_t stream, bool allow_pool, bool noalloc = false) {
     const int n = (int)djs.size();
     RingSlot* r = nullptr;
     isaac_status st = acquire_slot(ctx, &r);
@@ -857,7 +862,17 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     // render calls on the context stream set up the rays in a pass of their own
     // (one lane per ray) into the context's ray buffer
     la.dense_setup = 0;
-    if (allow_pool) {
+    if (noalloc) {
+        size_t off = 0;
+        for (int i = 0; i < n; ++i) {
+            DevJob& dj = r->host[i];
+            dj.rays = static_cast<char*>(ctx->noalloc_scratch) + off * ray_record_bytes();
+            off += (size_t)std::max(0, dj.cull[2] - dj.cull[0] + 1) * std::max(0, dj.cull[3] - dj.cull[1] + 1);
+        }
+        if (off * ray_record_bytes() > kNoAllocScratchBytes)
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "ray records exceed the scratch");   // checked before
+        la.dense_setup = off > 0 ? 1 : 0;
+    } else if (allow_pool) {
         size_t total = 0;
         for (int i = 0; i < n; ++i) {
             const DevJob& dj = r->host[i];
@@ -880,7 +895,7 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
         t1 = get_event(ctx);
         if (!t0 || !t1) return set_err(ctx, ISAAC_ERR_DEVICE, "hipEventCreate failed");
     }
-    const bool use_graph = n > 1 && !(flags & ISAAC_NO_GRAPH);
+    const bool use_graph = n > 1 && !(flags & ISAAC_NO_GRAPH) && !noalloc;
     if (use_graph) {
         if (!r->exec || r->g_jobs != n || r->g_tiles != tiles || r->g_grid != la.grid || r->g_src != la.max_src ||
             r->g_unroll != la.unroll || r->g_lanes != la.lanes || r->g_hint != la.waves_hint || r->g_sig != la.sig ||
@@ -917,7 +932,8 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
         if (t0) HIP_TRY(ctx, hipEventRecord(t0, stream));
         HIP_TRY(ctx, hipGraphLaunch(r->exec, stream));
         if (t1) HIP_TRY(ctx, hipEventRecord(t1, stream));
-    } else if (n == 1 && allow_pool && djs[0].pool && lanes >= 2 && lanes <= 16 && djs[0].mode == ISAAC_VOLUME &&
+    } else if (n == 1 && allow_pool && !noalloc && djs[0].pool && lanes >= 2 && lanes <= 16 &&
+               djs[0].mode == ISAAC_VOLUME &&
                (size_t)djs[0].width * djs[0].height * ray_record_bytes() < ((size_t)1 << 31) &&
                ensure_pool(ctx, (size_t)djs[0].width * djs[0].height * ray_record_bytes(), stream)) {
         // pooled schedule: compacted rays handed to lane groups as they free up
@@ -943,6 +959,12 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     if (t0) ctx->timed.emplace_back(t0, t1);
     HIP_TRY(ctx, hipEventRecord(r->done, stream));
     r->busy = true;
+    if (noalloc) {
+        // the ring event: a later call re-records it only after waiting for it (acquire_slot),
+        // so a query that sees newer work can only report this call's completion late
+        ctx->pending.push_back({seq, r->done, false});
+        return ISAAC_OK;
+    }
     hipEvent_t pe = get_event(ctx);
     if (!pe) return set_err(ctx, ISAAC_ERR_DEVICE, "hipEventCreate failed");
     HIP_TRY(ctx, hipEventRecord(pe, stream));
@@ -1101,7 +1123,7 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
 }
 
 isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int n, unsigned flags, bool need_out,
-                         hipStream_t stream, bool allow_derive) {
+                         hipStream_t stream, bool allow_derive, bool noalloc = false) {
     if (n < 1 || n > kMaxBatch || !jobs)
         return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "n_jobs must be 1..%d", kMaxBatch);
     std::vector<DevJob> djs(n);
@@ -1111,6 +1133,16 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
         isaac_status st = build_job(ctx, jobs[i], need_out, djs[i], &na);
         if (st) return st;
         max_src = std::max(max_src, na);
+    }
+    if (noalloc) {
+        // every job's ray records must fit the scratch together (checked before any update())
+        size_t rays = 0;
+        for (const DevJob& dj : djs)
+            rays += (size_t)std::max(0, dj.cull[2] - dj.cull[0] + 1) * std::max(0, dj.cull[3] - dj.cull[1] + 1);
+        if (rays * ray_record_bytes() > kNoAllocScratchBytes)
+            return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT,
+                           "the jobs' screen rectangles need %zu ray records of %zu bytes, above the %zu-byte "
+                           "scratch of calls that allocate nothing", rays, ray_record_bytes(), kNoAllocScratchBytes);
     }
     isaac_status st = prepare_sources(ctx, jobs, n);
     if (st) return st;
@@ -1174,7 +1206,7 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
     for (const auto& grp : groups) {
         int ms = 1;
         for (const DevJob& dj : grp) ms = std::max(ms, (int)dj.n_src);
-        st = enqueue_jobs(ctx, jobs, grp, ms, flags, stream, allow_derive);
+        st = enqueue_jobs(ctx, jobs, grp, ms, flags, stream, allow_derive, noalloc);
         if (st) return st;
     }
     (void)max_src;
@@ -1250,6 +1282,10 @@ isaac_status isaac_init(const isaac_init_desc* desc, isaac_context** out) {
     e = hipGetDeviceProperties(&prop, d.device);
     if (e != hipSuccess) return fail("hipGetDeviceProperties", e);
     ctx->n_cu = prop.multiProcessorCount;
+    {
+        const int rc = noalloc_scratch(d.device, &ctx->noalloc_scratch);   // d.device is current
+        if (rc != hipSuccess) return fail("scratch symbol address", (hipError_t)rc);
+    }
     int bpc = 1;
     if (raycast_occupancy(&bpc) == hipSuccess && bpc > 0) ctx->blocks_per_cu = bpc;
     if (d.stream) {
@@ -1456,6 +1492,16 @@ isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int
     isaac_status st = check_ctx(ctx);
     if (st) return st;
     return render_impl(ctx, jobs, n_jobs, flags, true, ctx->stream, true);
+}
+
+isaac_status isaac_render_noalloc(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags) {
+    isaac_status st = check_ctx(ctx);
+    if (st) return st;
+    if (flags & ~(ISAAC_ASYNC | ISAAC_NO_GRAPH | ISAAC_DIRECT))
+        return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT,
+                       "isaac_render_noalloc takes ISAAC_ASYNC, ISAAC_NO_GRAPH and ISAAC_DIRECT only");
+    if (!ctx->noalloc_scratch) return set_err(ctx, ISAAC_ERR_DEVICE, "no scratch address for this device");
+    return render_impl(ctx, jobs, n_jobs, flags | ISAAC_NO_GRAPH, true, ctx->stream, false, true);
 }
 
 isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const float* const* depth, int n_layers,

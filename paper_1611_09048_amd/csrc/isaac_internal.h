@@ -5,6 +5,8 @@
 
 #include <stdint.h>
 
+#include "isaac_mi355x.h"
+
 namespace isaac {
 
 constexpr int kMaxSources = 8;
@@ -140,6 +142,13 @@ int launch_strided_copy(const void* const* src_comp, const int64_t* src_stride, 
                         const int64_t* dst_stride, int esize, int f_dim, const int32_t lo[3],
                         const int32_t ext[3], void* stream);
 int raycast_occupancy(int* blocks_per_cu);
+// Device scratch of the render calls that allocate nothing (ray records of the
+// set-up pass): a static array of kNoAllocScratchBytes per device.  Looks up the
+// current device's copy (call with `device` current) once per device; *ptr is
+// its device address.
+constexpr size_t kNoAllocScratchBytes = ISAAC_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+int noalloc_scratch(int device, void** ptr);
 
 // Derived volume: the functor-chain output of up to 4 sources at every voxel
 // of [-g, N-1+g]^3, interleaved (n floats per voxel, x fastest).

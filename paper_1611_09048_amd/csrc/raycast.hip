@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "isaac_internal.h"
 
@@ -1729,6 +1730,30 @@ int launch_derive(const DeriveArgs& a, int sig, void* stream) {
     }
     hipLaunchKernelGGL(k, grid, dim3(256), 0, (hipStream_t)stream, a);
     return hipGetLastError();
+}
+
+// Scratch of the render entry point that allocates nothing: the ray records of
+// its set-up pass.  One copy per device, held until the process ends; every call
+// on a device uses that device's copy, so calls that overlap on one device (other
+// streams, other contexts) race.  Host code must not pass the array's name to a
+// kernel (in host code it is a stand-in, not a device address): it takes the
+// address noalloc_scratch() looked up for the device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+int noalloc_scratch(int device, void** ptr) {
+    static std::mutex lock;
+    static void* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices || !ptr) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> guard(lock);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the current device's copy
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 int raycast_occupancy(int* blocks_per_cu) {
