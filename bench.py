@@ -60,16 +60,15 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1611_09048_amd", "csrc", "raycast.hip")
 VIEW_SAMPLES = os.path.join(ROOT, "tests", "golden", "pic3_256_1080p_view_samples.json")
 
 
-def measured_counters():
+def measured_counters(shape):
     """Fields of the committed counter summary of the headline frame (HBM bytes
     per frame and per kernel, L2 hit rates), or None when the kernel source or
-    the tuner cache (which sets the launch's tile shape) changed since the
-    counters were taken."""
+    the launch's tile shape `shape` differ from the ones the counters were
+    taken with."""
     import hashlib
     try:
         text = open(COUNTERS).read()
         src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        tuned = hashlib.sha256(open(TUNED, "rb").read()).hexdigest()
     except OSError:
         return None
     fields = {}
@@ -77,22 +76,22 @@ def measured_counters():
         if ":" in line and not line.startswith(("#", "|", " ", "-")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("kernel source sha256") != src or fields.get("tuner cache sha256") != tuned:
+    if fields.get("kernel source sha256") != src or fields.get("tile shape") != ",".join(map(str, shape)):
         return None
     return fields
 
 
-def measured_traffic():
+def measured_traffic(shape):
     """HBM bytes (fetched + written, calibrated) per headline frame from the counters, or None."""
-    f = measured_counters()
+    f = measured_counters(shape)
     if f is None or "traffic_bytes_per_frame" not in f:
         return None
     return int(f["traffic_bytes_per_frame"])
 
 
-def measured_l2_hit_rate():
+def measured_l2_hit_rate(shape):
     """L2 hit rate per kernel of the headline frame from the counters, or None."""
-    f = measured_counters()
+    f = measured_counters(shape)
     if f is None:
         return None
     out = {k[len("l2_hit_rate "):]: float(v) for k, v in f.items() if k.startswith("l2_hit_rate ")}
@@ -289,12 +288,18 @@ def frames(ctx, sc, steps, warmup, view_reps=0, log_prefix=""):
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
-        ctx.render([jobs[k % len(jobs)]], ASYNC | TIMING)
+        ctx.render([jobs[k % len(jobs)]], ASYNC)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kernel_ms, n_kernels = ctx.timing()
     frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    # the ray-casting kernel alone, bracketed by the library's events (which add a
+    # marker between the passes, so not inside the timed frames): one pass over the views
+    ctx.timing()
+    for j in jobs:
+        ctx.render([j], ASYNC | TIMING)
+    torch.cuda.synchronize()
+    kernel_ms, n_kernels = ctx.timing()
     total = sum(samples[k % len(jobs)] for k in range(steps))
     out = dict(gsps=total / elapsed / 1e9, elapsed=elapsed, kernel_ms=kernel_ms / max(n_kernels, 1),
                frame_ms=frame_ms, samples=samples, gpu_samples=gpu_samples, counted_by=counted_by, shape=shape,
@@ -437,6 +442,16 @@ def batch64(ctx, steps):
         return ms / n
 
     shape = apply_tuning(ctx, "batch64:f32x1", classes, time_jobs)
+    # one launch shares the kernel variant; each size class then takes its own tile shape
+    cache = autotune.load_cache(TUNED)
+    n_before = len(cache)
+    per_class = autotune.refine_per_class(ctx, classes, shape, time_jobs, cache=cache, sig="batch64:f32x1:class",
+                                          log=log)
+    if len(cache) != n_before:
+        try:
+            autotune.save_cache(TUNED, cache)
+        except OSError:
+            pass
     ctx.render([device.render_job(sc, vid, imgs[vid], cnts[vid]) for vid, sc in enumerate(scs)])
     samples = int(sum(int(c.to(torch.int64).sum().item()) for c in cnts))
     ctx.render(jobs, ASYNC)
@@ -451,6 +466,7 @@ def batch64(ctx, steps):
     res = dict(jobs=len(scs), samples_per_batch=samples, launch_ms=round(el * 1e3 / steps, 4),
                graph_ms=round(ms / max(n, 1), 4), gsamples_per_s=round(samples * steps / el / 1e9, 3),
                jobs_per_s=round(len(scs) * steps / el, 1), tile_shape=list(shape),
+               tile_shape_per_class={str(c): list(v) for c, v in per_class.items()},
                rays=int(sum(sc.width * sc.height for sc in scs)))
     log(f"bench: batch64 {res}")
     del vols
@@ -476,7 +492,13 @@ def serving(ctx, duration: float, rate: float, n: int = 512, depth: int = 256, f
     out.update(volume=list(dims), offered_rate=rate, requests=len(reqs), frozen=freeze)
     log(f"bench: serving {out}")
     del vol
-    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+    def rnd(v):
+        if isinstance(v, float):
+            return round(v, 4)
+        if isinstance(v, dict):
+            return {k: rnd(x) for k, x in v.items()}
+        return v
+    return {k: rnd(v) for k, v in out.items()}
 
 
 def iso_frames(ctx, n: int, width: int, height: int, steps: int = 26):
@@ -607,7 +629,7 @@ def check_frame_timing(frame_ms, kernel_ms):
                            f"({kernel_ms:.4f} ms): they do not bracket the render")
 
 
-def rooflines(frame_ms, kernel_ms, algo_bytes, samples_per_frame):
+def rooflines(frame_ms, kernel_ms, algo_bytes, samples_per_frame, shape=()):
     """(HBM roofline of the whole frame, ALU roofline of the ray-casting kernel).
 
     HBM: every stored source byte and the image once (the frame's algorithmic
@@ -621,7 +643,7 @@ def rooflines(frame_ms, kernel_ms, algo_bytes, samples_per_frame):
     if gbs > HBM_PEAK_GBS:
         raise RuntimeError(f"{gbs:.0f} GB/s of algorithmic bytes is above the HBM peak: the frame time is wrong")
     hbm = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
-               traffic=measured_traffic(), l2_hit_rate=measured_l2_hit_rate(),
+               traffic=measured_traffic(shape), l2_hit_rate=measured_l2_hit_rate(shape),
                scope="one frame: derive_kernel, prepass_kernel and raycast_kernel, one stream",
                algorithmic_bytes_per_frame=int(algo_bytes), frame_ms_mean=round(mean_ms, 4))
     flops = FLOPS_PER_SAMPLE * samples_per_frame
@@ -677,7 +699,7 @@ def main():
         return
     fr = frames(ctx, sc, args.steps, args.warmup, view_reps=args.view_reps)
     roofline, roofline_alu = rooflines(fr["frame_ms"], fr["kernel_ms"], fr["field_bytes"] + fr["image_bytes"],
-                                       float(np.mean(fr["samples"])))
+                                       float(np.mean(fr["samples"])), fr["shape"])
     out = dict(metric=METRIC, value=round(fr["gsps"], 3), unit="Gsamples/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(fr["elapsed"] * 1e3 / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype=args.dtype, data="synthetic",
@@ -720,6 +742,7 @@ def main():
         extras["batch64"] = batch64(ctx, 10)
         extras["serving"] = serving(ctx, args.serve_seconds, 200.0)
         extras["serving_stress"] = serving(ctx, max(2.0, args.serve_seconds / 2), 2000.0)
+        extras["serving_stress_5000"] = serving(ctx, max(2.0, args.serve_seconds / 4), 5000.0)
         extras["serving_unfrozen"] = serving(ctx, max(2.0, args.serve_seconds / 2), 200.0, freeze=False)
         extras["served_readback_ms"] = served_readback(ctx)
         out["extras"] = extras

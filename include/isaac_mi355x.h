@@ -117,6 +117,13 @@ const char* isaac_init_error(void);
  * components, padded rows, any axis order and reversed axes are all read in
  * place.  Voxel (x,y,z) component c is at comp[c] + x*stride[0] +
  * y*stride[1] + z*stride[2] for x in [-guard, Nx-1+guard] and likewise in y, z.
+ * Limits (ISAAC_ERR_INVALID_ARGUMENT otherwise, checked by isaac_set_sources):
+ * the kernels address a source with 32-bit byte offsets, so per axis
+ * |stride| * (N + 2*g) must stay below 2 GiB, g = min(guard, 1), and so must
+ * the byte range the reachable voxels span (all components); strides and
+ * component addresses must be multiples of the element size.  A zero stride
+ * repeats the field along that axis.  A non-persistent source's packed copy
+ * must also stay below 2 GiB.
  */
 typedef struct {
     const char* name;                 /* copied; may be NULL */
@@ -163,7 +170,8 @@ typedef struct {
     int volume_id;
     int width, height;                /* image size in pixels, >= 1 */
     int projection;                   /* ISAAC_PERSPECTIVE or ISAAC_ORTHOGRAPHIC */
-    double eye[3], center[3], up[3];  /* camera, index-space units; right = forward x up */
+    double eye[3], center[3], up[3];  /* camera, index-space units; right = forward x up; eye != center;
+                                         up not within 1e-6 rad of the view direction */
     double fovy_deg;                  /* perspective: vertical field of view, (0,180) */
     double ortho_height;              /* orthographic: image height in voxels, > 0 */
     double step;                      /* sample spacing along the ray in voxels, > 0 */

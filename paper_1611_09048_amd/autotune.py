@@ -117,3 +117,47 @@ def tune(ctx: binding.Context, jobs_by_class: Dict[int, Sequence[binding.RenderD
         if cache is not None:
             cache[key] = list(best[cls])
     return best
+
+
+def class_shapes(lanes: int) -> List[Tuple[int, int]]:
+    """(wave_w, waves_x) tile shapes a size class can take at a given lanes-per-ray count."""
+    return [(w, x) for w in WAVE_W if w <= 64 // lanes and (w >= 8 or w == 64 // lanes) for x in WAVES_X]
+
+
+def refine_per_class(ctx: binding.Context, classes: Sequence[int], base: Tuple, time_batch,
+                     cache: Optional[Dict[str, list]] = None, arch: str = "gfx950", sig: str = "",
+                     log=None) -> Dict[int, Tuple]:
+    """Tile shape per size class inside one batched launch.
+
+    The jobs of a batch share one kernel variant (lanes per ray, unroll,
+    min_waves and the schedule are common to the launch), but every job keeps
+    its own tile shape, so each size class can take the (wave_w, waves_x) that
+    suits its image size.  Starting from `base` for every class, each class in
+    turn tries every tile shape with the other classes at their current shape,
+    keeping the fastest whole-batch time (`time_batch()`, ms).  Cached per class
+    under the signature `sig`."""
+    shapes = {c: tuple(base) for c in classes}
+    keys = {c: cache_key(arch, c, sig) for c in classes}
+    if cache is not None and all(k in cache for k in keys.values()):
+        for c in classes:
+            shapes[c] = tuple(cache[keys[c]])
+            ctx.set_tile_shape(c, *shapes[c])
+        return shapes
+    for c in classes:
+        ctx.set_tile_shape(c, *shapes[c])
+    for c in classes:
+        times = {}
+        for w, x in class_shapes(base[3]):
+            cand = (w, x) + tuple(base[2:])
+            ctx.set_tile_shape(c, *cand)
+            times[cand] = time_batch()
+        shapes[c] = pick(times)
+        ctx.set_tile_shape(c, *shapes[c])
+        if log:
+            log(f"autotune batch class {c}: {shapes[c]} {times[shapes[c]]:.4f} ms "
+                f"(shared shape {tuple(base)}: {times.get(tuple(base), float('nan')):.4f} ms)")
+    if cache is not None:
+        for c in classes:
+            cache[keys[c]] = list(shapes[c])
+    return shapes
+

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libisaac_mi355x.so")
-SOURCES = ["raycast.hip", "jpeg.hip", "jpeg_tables.cpp", "isaac_api.cpp"]
+SOURCES = ["raycast.hip", "jpeg.hip", "jpeg_tables.cpp", "host_logic.cpp", "isaac_api.cpp"]
 ARCH = "gfx950"
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -130,6 +130,9 @@ struct LaunchArgs {
 };
 
 int launch_prepass(const LaunchArgs& a, void* stream);               // fill outside the rectangles, ray setup
+// The same for one job passed by value, which the kernel also stores at dst
+// (the device job block the ray-casting launch reads).
+int launch_prepass_one(const DevJob& job, DevJob* dst, unsigned fill_blocks, int dense, void* stream);
 int launch_raycast(const LaunchArgs& a, void* stream);               // returns hipError_t
 int launch_reset_counter(int* counter, void* stream);
 // Pooled schedule of one job (lanes >= 2): ray setup with compaction into

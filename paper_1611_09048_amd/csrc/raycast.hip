@@ -1517,6 +1517,23 @@ __global__ __launch_bounds__(256) void prepass_kernel(const DevJob* __restrict__
         ray_setup_dense(J, b - nb, nb);
 }
 
+// One job: the fill and ray setup as above, reading the job block from the
+// kernel arguments, and the block stored to device memory for the
+// ray-casting launch that follows (no separate host-to-device copy).
+__global__ __launch_bounds__(256) void prepass_one_kernel(const DevJob job, DevJob* __restrict__ dst, int nb,
+                                                          int dense) {
+    const int b = (int)blockIdx.x;
+    if (b == 0) {
+        const uint32_t* s = reinterpret_cast<const uint32_t*>(&job);
+        uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+        for (int i = (int)threadIdx.x; i < (int)(sizeof(DevJob) / 4); i += 256) d[i] = s[i];
+    }
+    if (b < nb)
+        fill_outside(job, b, nb);
+    else if (dense)
+        ray_setup_dense(job, b - nb, nb);
+}
+
 __global__ void reset_counter_kernel(int* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
@@ -1599,6 +1616,13 @@ int launch_prepass(const LaunchArgs& a, void* stream) {
     else
         hipLaunchKernelGGL(fill_outside_kernel, dim3(a.fill_blocks, (unsigned)a.n_jobs), dim3(256), 0,
                            (hipStream_t)stream, a.jobs);
+    return hipGetLastError();
+}
+
+int launch_prepass_one(const DevJob& job, DevJob* dst, unsigned fill_blocks, int dense, void* stream) {
+    static_assert(sizeof(DevJob) % 4 == 0 && sizeof(DevJob) + 16 <= 4096, "the job block is a kernel argument");
+    hipLaunchKernelGGL(prepass_one_kernel, dim3((dense ? 2 : 1) * fill_blocks), dim3(256), 0, (hipStream_t)stream,
+                       job, dst, (int)fill_blocks, dense);
     return hipGetLastError();
 }
 

@@ -6,8 +6,11 @@ and memory free up, launching whatever is waiting as one batched render
 streams, so work from successive batches overlaps on the device.  Sources
 and transfer tables stay resident; each request carries its own camera,
 table handles and clipping planes, so its image does not depend on what it
-was batched with.  Latency runs from arrival to the first poll that sees the
-request's image complete.
+was batched with.  Latency runs from the request's scheduled arrival (not the
+moment the loop notices it, so a busy loop cannot hide its own delay) to the
+first poll that sees the request's image complete; each record also keeps when
+the loop noticed the request and when it was submitted, and the executor the
+host time of every submit call, so a tail can be traced to its phase.
 
 The scheduling logic talks to an Executor; `DeviceExecutor` drives the HIP
 library, `FakeExecutor` (tests) simulates completion times on a fake clock.
@@ -40,9 +43,10 @@ class Job:
 class Record:
     rid: int
     client: int
-    arrival: float
-    submitted: float = math.nan
-    done: float = math.nan
+    arrival: float                 # scheduled arrival on the server clock
+    noticed: float = math.nan      # when the loop took the request in
+    submitted: float = math.nan    # when its batch's submit call returned
+    done: float = math.nan         # first poll that saw its image complete
     batch: int = -1
     width: int = 0
     height: int = 0
@@ -50,6 +54,16 @@ class Record:
     @property
     def latency(self) -> float:
         return self.done - self.arrival
+
+    @property
+    def queued(self) -> float:
+        """Arrival to submission: waiting in the loop, for a slot or for memory."""
+        return self.submitted - self.arrival
+
+    @property
+    def service(self) -> float:
+        """Submission to the poll that saw the image: device time plus polling delay."""
+        return self.done - self.submitted
 
 
 class Executor:
@@ -125,6 +139,7 @@ class DeviceExecutor(Executor):
         self.ticket_handles: Dict[int, list] = {}
         self.latest: Dict[tuple, tuple] = {}          # (client, source) -> newest table key
         self.submits = 0
+        self.submit_s: List[float] = []               # host time of each submit call (tables, launch)
 
     def camera(self, direction):
         c = np.array(self.dims, dtype=np.float64) / 2.0
@@ -151,6 +166,7 @@ class DeviceExecutor(Executor):
         return d, hs
 
     def submit(self, jobs):
+        t0 = time.perf_counter()
         descs, hss = zip(*[self.desc(j) for j in jobs])
         for j in jobs:
             for key in j.tf_key:
@@ -158,6 +174,7 @@ class DeviceExecutor(Executor):
                 if cs not in self.latest or self.latest[cs][2] < key[2]:
                     self.latest[cs] = key
         tickets = self.ctx.submit_batch(list(descs))
+        self.submit_s.append(time.perf_counter() - t0)
         if tickets is None:
             return None
         for t, hs in zip(tickets, hss):
@@ -211,8 +228,11 @@ class Server:
         self.refusals = 0
         self.errors: List[str] = []
 
-    def arrive(self, rid: int, client: int, job: Job, width: int, height: int):
-        rec = Record(rid=rid, client=client, arrival=self.clock(), width=width, height=height)
+    def arrive(self, rid: int, client: int, job: Job, width: int, height: int, at: Optional[float] = None):
+        """Take a request in; `at` is its scheduled arrival on the server clock (default: now)."""
+        now = self.clock()
+        rec = Record(rid=rid, client=client, arrival=now if at is None else at, noticed=now, width=width,
+                     height=height)
         self.waiting.append((rec, job))
 
     def step(self) -> int:
@@ -275,9 +295,22 @@ class Server:
                    batches=self.n_batches, refusals=self.refusals, duration_s=duration,
                    frames_per_s=len(self.records) / duration if duration > 0 else 0.0)
         if lat.size:
+            q = np.array([r.queued for r in self.records]) * 1e3
+            sv = np.array([r.service for r in self.records]) * 1e3
+            nd = np.array([r.noticed - r.arrival for r in self.records]) * 1e3
             out.update(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                        mean_ms=float(lat.mean()), max_ms=float(lat.max()),
-                       mean_batch=float(len(self.records) / max(1, self.n_batches)))
+                       mean_batch=float(len(self.records) / max(1, self.n_batches)),
+                       queued_ms=dict(p50=float(np.percentile(q, 50)), p99=float(np.percentile(q, 99)),
+                                      max=float(q.max())),
+                       service_ms=dict(p50=float(np.percentile(sv, 50)), p99=float(np.percentile(sv, 99)),
+                                       max=float(sv.max())),
+                       notice_delay_ms=dict(p99=float(np.percentile(nd, 99)), max=float(nd.max())))
+            sub = getattr(self.ex, "submit_s", None)
+            if sub:
+                sub = np.array(sub) * 1e3
+                out["submit_call_ms"] = dict(p50=float(np.percentile(sub, 50)), p99=float(np.percentile(sub, 99)),
+                                             max=float(sub.max()))
         return out
 
 
@@ -290,7 +323,7 @@ def run(server: Server, requests, clock, sleep=time.sleep, make_job=None, drain:
         now = clock() - t0
         while i < len(reqs) and reqs[i].arrival <= now:
             r = reqs[i]
-            server.arrive(i, r.client, make_job(i, r), r.width, r.height)
+            server.arrive(i, r.client, make_job(i, r), r.width, r.height, at=t0 + r.arrival)
             i += 1
         worked = server.step()
         if not worked:

@@ -49,3 +49,33 @@ def test_cache_round_trip_and_pick(tmp_path):
     assert autotune.pick(times) == (4, 1, 1, 16, 4, 0)       # ties go to the smaller shape
     for a, b in itertools.combinations(sorted(times), 2):
         assert a < b
+
+
+class _FakeCtx:
+    def __init__(self):
+        self.shapes = {}
+
+    def set_tile_shape(self, cls, *shape):
+        self.shapes[cls] = tuple(shape)
+
+
+def test_per_class_refinement_keeps_the_launch_variant_and_caches():
+    """Each class takes the tile shape that times fastest with the others fixed; the
+    kernel variant (unroll, lanes, min_waves, schedule) stays the shared one."""
+    ctx = _FakeCtx()
+    base = (8, 2, 1, 4, 0, 1)
+    best = {7: (16, 1), 8: (8, 4), 9: (16, 4), 10: (8, 2)}
+
+    def time_batch():
+        return sum(0.0 if ctx.shapes[c][:2] == best[c] else 1.0 + 0.01 * ctx.shapes[c][0] for c in best)
+
+    cache = {}
+    got = autotune.refine_per_class(ctx, sorted(best), base, time_batch, cache=cache, sig="b:class")
+    for c, (w, x) in best.items():
+        assert got[c] == (w, x) + base[2:] and ctx.shapes[c] == got[c]
+        assert cache[autotune.cache_key("gfx950", c, "b:class")] == list(got[c])
+    # a second run takes the cache and times nothing
+    ctx2 = _FakeCtx()
+    got2 = autotune.refine_per_class(ctx2, sorted(best), base, lambda: 1 / 0, cache=cache, sig="b:class")
+    assert got2 == got and ctx2.shapes == ctx.shapes
+    assert all(s in autotune.class_shapes(4) for s in best.values())

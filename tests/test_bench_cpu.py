@@ -1,6 +1,6 @@
 """Host logic of bench.py: the measured HBM traffic and L2 hit rates are
-reported only while the kernel source and the tuner cache are the ones the
-counters were taken with; frame timings that cannot bracket the render, or
+reported only while the kernel source and the launch's tile shape are the
+ones the counters were taken with; frame timings that cannot bracket the render, or
 that put the frame above the HBM peak, are refused."""
 
 import hashlib
@@ -11,48 +11,46 @@ import pytest
 import bench
 
 
-def _setup(tmp_path, src=b"kernel v1", tuned=b'{"a": [1]}', value=123456):
+SHAPE = (4, 1, 1, 16, 4, 0)
+
+
+def _setup(tmp_path, src=b"kernel v1", value=123456):
     k = tmp_path / "raycast.hip"
-    t = tmp_path / "tuned.json"
     c = tmp_path / "counters.md"
     k.write_bytes(src)
-    t.write_bytes(tuned)
     c.write_text(f"# counters\nkernel source sha256: {hashlib.sha256(src).hexdigest()}\n"
-                 f"tuner cache sha256: {hashlib.sha256(tuned).hexdigest()}\n\n"
+                 f"tile shape: 4,1,1,16,4,0\n\n"
                  f"| kernel | fetch |\n|---|---|\n| raycast_kernel | 1 |\n\n"
                  f"traffic_bytes_per_frame: {value}\n"
                  f"l2_hit_rate raycast_kernel: 0.75\nl2_hit_rate derive_kernel: 0.125\n")
-    return k, t, c
+    return k, c
 
 
-def _patch(monkeypatch, k, t, c):
+def _patch(monkeypatch, k, c):
     monkeypatch.setattr(bench, "KERNEL_SRC", str(k))
-    monkeypatch.setattr(bench, "TUNED", str(t))
     monkeypatch.setattr(bench, "COUNTERS", str(c))
 
 
 def test_traffic_reported_when_hashes_match(tmp_path, monkeypatch):
-    k, t, c = _setup(tmp_path)
-    _patch(monkeypatch, k, t, c)
-    assert bench.measured_traffic() == 123456
-    assert bench.measured_l2_hit_rate() == {"raycast_kernel": 0.75, "derive_kernel": 0.125}
+    k, c = _setup(tmp_path)
+    _patch(monkeypatch, k, c)
+    assert bench.measured_traffic(SHAPE) == 123456
+    assert bench.measured_l2_hit_rate(SHAPE) == {"raycast_kernel": 0.75, "derive_kernel": 0.125}
 
 
-def test_traffic_withheld_after_a_kernel_or_cache_change(tmp_path, monkeypatch):
-    k, t, c = _setup(tmp_path)
-    _patch(monkeypatch, k, t, c)
+def test_traffic_withheld_after_a_kernel_or_shape_change(tmp_path, monkeypatch):
+    k, c = _setup(tmp_path)
+    _patch(monkeypatch, k, c)
     k.write_bytes(b"kernel v2")
-    assert bench.measured_traffic() is None
-    assert bench.measured_l2_hit_rate() is None
+    assert bench.measured_traffic(SHAPE) is None
+    assert bench.measured_l2_hit_rate(SHAPE) is None
     k.write_bytes(b"kernel v1")
-    t.write_bytes(b'{"a": [2]}')
-    assert bench.measured_traffic() is None
-    t.write_bytes(b'{"a": [1]}')
-    assert bench.measured_traffic() == 123456
-    c.write_text(c.read_text().replace("tuner cache sha256", "tuner sha"))
-    assert bench.measured_traffic() is None          # a summary without the cache hash is stale
+    assert bench.measured_traffic((8, 2, 1, 16, 4, 0)) is None        # another tile shape
+    assert bench.measured_traffic(SHAPE) == 123456
+    c.write_text(c.read_text().replace("tile shape", "shape"))
+    assert bench.measured_traffic(SHAPE) is None          # a summary without the shape is stale
     monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "missing.md"))
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic(SHAPE) is None
 
 
 def test_rooflines_from_frame_and_kernel_times(tmp_path, monkeypatch):
