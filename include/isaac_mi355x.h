@@ -89,7 +89,8 @@ typedef struct isaac_context isaac_context;   /* opaque */
 typedef struct {
     int device;                  /* HIP device ordinal */
     void* stream;                /* hipStream_t to enqueue on (borrowed, never destroyed); NULL: see flags */
-    size_t mem_budget_bytes;     /* serving: device bytes for library-owned output images; 0: 1 GiB */
+    size_t mem_budget_bytes;     /* serving: device bytes for library-owned output images, allocated as one
+                                    block at the first isaac_submit*; 0: 1 GiB */
     int max_inflight;            /* serving: outstanding submitted requests; 0: 64 */
     int max_volumes;             /* volume ids 0..max_volumes-1; 0: 256 */
     unsigned flags;              /* ISAAC_INIT_* bits; other bits: ISAAC_ERR_INVALID_ARGUMENT */
@@ -353,8 +354,11 @@ isaac_status isaac_get_tile_shape(isaac_context* ctx, int size_class, int* wave_
 /* ---- serving: library-owned output images admitted against mem_budget ---- */
 
 /* Enqueue one render into a library-owned image (job->out_rgba and
- * job->out_samples are ignored).  Returns ISAAC_ERR_BUSY when max_inflight
- * requests are outstanding or the image does not fit the memory budget. */
+ * job->out_samples are ignored).  Images are carved from the memory budget
+ * (one device block, allocated at the first submission; images in 256-byte
+ * granules, first fit), so later submissions allocate no device memory.
+ * Returns ISAAC_ERR_BUSY when max_inflight requests are outstanding or the
+ * image does not fit a free run of the budget. */
 isaac_status isaac_submit(isaac_context* ctx, const isaac_render_desc* job, uint64_t* out_ticket);
 
 /* Several requests as one batched launch; tickets[i] receives job i's ticket.

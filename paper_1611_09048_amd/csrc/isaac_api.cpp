@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <string>
 #include <vector>
@@ -115,6 +116,68 @@ struct Ticket {
     bool done = false;
 };
 
+// Serving images: one device allocation of the memory budget, made at the
+// first submission and carved into images first fit (256-byte granules, free
+// neighbours merged on release), so no request allocates or frees device
+// memory (hipFree would wait for the whole device).
+class ImageArena {
+public:
+    static constexpr size_t kGranule = 256;
+    bool ready() const { return base_ != nullptr; }
+    bool init(size_t bytes) {
+        bytes = bytes / kGranule * kGranule;
+        if (bytes == 0 || hipMalloc((void**)&base_, bytes) != hipSuccess) {
+            base_ = nullptr;
+            return false;
+        }
+        size_ = bytes;
+        free_.clear();
+        free_[0] = bytes;
+        return true;
+    }
+    void destroy() {
+        if (base_) (void)hipFree(base_);
+        base_ = nullptr;
+        size_ = 0;
+        free_.clear();
+    }
+    static size_t rounded(size_t bytes) { return (bytes + kGranule - 1) / kGranule * kGranule; }
+    // first free run that fits; nullptr if none does
+    float* take(size_t bytes) {
+        bytes = rounded(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, left = it->second - bytes;
+            free_.erase(it);
+            if (left) free_[off + bytes] = left;
+            return reinterpret_cast<float*>(base_ + off);
+        }
+        return nullptr;
+    }
+    void give(float* p, size_t bytes) {
+        bytes = rounded(bytes);
+        size_t off = (size_t)(reinterpret_cast<char*>(p) - base_);
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+
+private:
+    char* base_ = nullptr;
+    size_t size_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> bytes
+};
+
 struct TileShape {
     int wave_w = 8, waves_x = 2, unroll = 1, lanes = 1, waves_hint = 0, pool = 0;
 };
@@ -148,8 +211,7 @@ struct isaac_context {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
     // serving
     std::map<uint64_t, Ticket> tickets;
-    std::multimap<size_t, float*> image_cache;
-    size_t cached = 0;
+    ImageArena images;                 // served images, within the memory budget
     uint64_t next_ticket = 1;
     void* enc_buf = nullptr;           // RGBA8 staging of isaac_read_image_rgba8 / _jpeg
     isaac::JpegWork* jpeg = nullptr;   // JPEG encoder scratch, created on first use
@@ -1130,7 +1192,7 @@ void isaac_destroy(isaac_context* ctx) {
         if (kv.second.out) hipFree(kv.second.out);
         if (kv.second.ev) hipEventDestroy(kv.second.ev);
     }
-    for (auto& kv : ctx->image_cache) hipFree(kv.second);
+    ctx->images.destroy();
     for (auto& r : ctx->ring) {
         if (r.exec) hipGraphExecDestroy(r.exec);
         if (r.graph) hipGraphDestroy(r.graph);
@@ -1451,7 +1513,7 @@ isaac_status isaac_submit_batch(isaac_context* ctx, const isaac_render_desc* job
     for (int i = 0; i < n; ++i) {
         if (jobs[i].width < 1 || jobs[i].height < 1 || jobs[i].width > 32768 || jobs[i].height > 32768)
             return set_err(ctx, ISAAC_ERR_INVALID_ARGUMENT, "image size out of range");
-        need += (size_t)jobs[i].width * jobs[i].height * 4 * sizeof(float);
+        need += ImageArena::rounded((size_t)jobs[i].width * jobs[i].height * 4 * sizeof(float));
     }
     size_t inflight = ctx->tickets.size();
     if ((int)(inflight + n) > ctx->max_inflight || ctx->used + need > ctx->budget)
@@ -1467,55 +1529,49 @@ isaac_status isaac_submit_batch(isaac_context* ctx, const isaac_render_desc* job
         st = build_job(ctx, js[i], true, tmp, &na);
         if (st) return st;
     }
+    if (!ctx->images.ready() && !ctx->images.init(ctx->budget))
+        return set_err(ctx, ISAAC_ERR_OUT_OF_MEMORY, "no device memory for the %zu-byte serving budget", ctx->budget);
     std::vector<Ticket> made;
+    auto give_back = [&]() {
+        for (auto& m : made) ctx->images.give(m.out, m.bytes);
+    };
     for (int i = 0; i < n; ++i) {
         Ticket t;
-        t.id = ctx->next_ticket++;
-        t.bytes = (size_t)jobs[i].width * jobs[i].height * 4 * sizeof(float);
+        t.bytes = (size_t)jobs[i].width * jobs[i].height * 4 * sizeof(float);   // the image (the arena rounds)
         t.width = jobs[i].width;
         t.height = jobs[i].height;
-        auto it = ctx->image_cache.find(t.bytes);
-        if (it != ctx->image_cache.end()) {
-            t.out = it->second;
-            ctx->image_cache.erase(it);
-            ctx->cached -= t.bytes;
-        } else if (hipMalloc((void**)&t.out, t.bytes) != hipSuccess) {
-            for (auto& m : made) {
-                ctx->image_cache.emplace(m.bytes, m.out);
-                ctx->cached += m.bytes;
-            }
-            return set_err(ctx, ISAAC_ERR_OUT_OF_MEMORY, "image allocation failed");
+        t.out = ctx->images.take(t.bytes);
+        if (!t.out) {
+            give_back();
+            return set_err(ctx, ISAAC_ERR_BUSY, "admission refused: no free run of %zu bytes in the budget "
+                           "(%zu of %zu bytes in use)", t.bytes, ctx->used, ctx->budget);
         }
         js[i].out_rgba = t.out;
         made.push_back(t);
     }
+    std::vector<hipEvent_t> evs(n, nullptr);
+    for (int i = 0; i < n; ++i)
+        if (!(evs[i] = get_event(ctx))) {
+            for (hipEvent_t e : evs) put_event(ctx, e);
+            give_back();
+            return set_err(ctx, ISAAC_ERR_DEVICE, "hipEventCreate failed");
+        }
     hipStream_t s = ctx->serve_streams[ctx->serve_rr];
     ctx->serve_rr = (ctx->serve_rr + 1) % (int)ctx->serve_streams.size();
     st = render_impl(ctx, js.data(), n, ISAAC_ASYNC | ISAAC_NO_GRAPH, true, s, false);
     if (st) {
-        for (auto& m : made) {
-            ctx->image_cache.emplace(m.bytes, m.out);
-            ctx->cached += m.bytes;
-        }
+        for (hipEvent_t e : evs) put_event(ctx, e);
+        give_back();
         return st;
     }
-    hipEvent_t ev = nullptr;
     for (int i = 0; i < n; ++i) {
         Ticket& t = made[i];
-        t.ev = get_event(ctx);
-        if (!t.ev) return set_err(ctx, ISAAC_ERR_DEVICE, "hipEventCreate failed");
+        t.id = ctx->next_ticket++;
+        t.ev = evs[i];
         HIP_TRY(ctx, hipEventRecord(t.ev, s));
-        ctx->used += t.bytes;
+        ctx->used += ImageArena::rounded(t.bytes);
         tickets[i] = t.id;
         ctx->tickets[t.id] = t;
-    }
-    (void)ev;
-    // keep the cache of freed images within what the budget leaves
-    while (ctx->cached > 0 && ctx->cached + ctx->used > ctx->budget) {
-        auto it = ctx->image_cache.begin();
-        ctx->cached -= it->first;
-        hipFree(it->second);
-        ctx->image_cache.erase(it);
     }
     return ISAAC_OK;
 }
@@ -1548,9 +1604,8 @@ isaac_status isaac_release(isaac_context* ctx, uint64_t ticket) {
     Ticket& t = it->second;
     if (!t.done) HIP_TRY(ctx, hipEventSynchronize(t.ev));
     put_event(ctx, t.ev);
-    ctx->used -= t.bytes;
-    ctx->image_cache.emplace(t.bytes, t.out);
-    ctx->cached += t.bytes;
+    ctx->used -= ImageArena::rounded(t.bytes);
+    ctx->images.give(t.out, t.bytes);
     ctx->tickets.erase(it);
     update_completed(ctx);
     return ISAAC_OK;

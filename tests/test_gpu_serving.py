@@ -90,7 +90,32 @@ def test_admission_refused_when_budget_is_full(ctx):
     for t in tickets:
         ctx.release(t)
     assert ctx.serving_usage()[0] == 0
-    assert ctx.submit(job) is not None
+    t = ctx.submit(job)
+    assert t is not None
+    ctx.release(t)
+    del vol
+
+
+def test_budget_runs_merge_after_release_in_any_order(ctx):
+    """Served images are carved from one block of the budget: images of three sizes
+    released out of order leave one free run again, so an image of the whole budget
+    (64 MiB) is admitted afterwards; an image larger than the budget never is."""
+    from paper_1611_09048_amd import device
+    sc = configs.pic3(n=16, width=64, height=64)
+    vol = device.upload_volume(ctx, sc, 9)
+    out = device.new_image(sc)
+    sizes = [(1024, 1024), (512, 512), (2048, 1024), (512, 512)]
+    tickets = [ctx.submit(device.render_job(sc.with_(width=w, height=h), 9, out)) for w, h in sizes]
+    assert all(t is not None for t in tickets)
+    for k in (1, 0, 3, 2):
+        ctx.release(tickets[k])
+    assert ctx.serving_usage()[0] == 0
+    whole = ctx.submit(device.render_job(sc.with_(width=2048, height=2048), 9, out))
+    assert whole is not None                       # 2048 x 2048 x 16 B = the 64 MiB budget
+    assert ctx.submit(device.render_job(sc, 9, out)) is None       # nothing left beside it
+    ctx.release(whole)
+    assert ctx.submit(device.render_job(sc.with_(width=4096, height=2048), 9, out)) is None
+    assert ctx.serving_usage()[0] == 0
     del vol
 
 
