@@ -256,9 +256,13 @@ isaac_status isaac_render_noalloc(isaac_context* ctx, const isaac_render_desc* j
 /* Sort-last compositing (Sec. 3.1, Fig. "whole concept"): per pixel, order the
  * n_layers partial images by their depth images (out_depth of the brick
  * renders) and combine them front to back:
- * (C, A) o (C', A') = (C + (1-A) C', A + (1-A) A').  rgba and depth are host
- * arrays of n_layers device pointers (1..16); out is device RGBA32F.  Runs on
- * the context stream; without ISAAC_ASYNC it waits for the result. */
+ * (C, A) o (C', A') = (C + (1-A) C', A + (1-A) A'), equal depths in layer
+ * order.  A depth of +inf marks a pixel the layer does not cover (a brick
+ * render writes +inf and colour (0,0,0,0) where it keeps no scan point): the
+ * layer's colour there is not read; a pixel no layer covers is (0,0,0,0).
+ * rgba and depth are host arrays of n_layers device pointers (1..16); out is
+ * device RGBA32F.  Runs on the context stream; without ISAAC_ASYNC it waits
+ * for the result. */
 isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const float* const* depth, int n_layers,
                              int width, int height, float* out, unsigned flags);
 

@@ -1240,14 +1240,24 @@ struct CompositeArgs {
     float4* out;
 };
 
+// A layer without a scan point at a pixel has depth +inf and colour
+// (0,0,0,0); compositing it changes nothing (C + T*0 = C exactly), so a pixel
+// reads the colours of its layers with a finite depth only, and a pixel no
+// layer reaches (most of the frame) writes transparent black at once.
 __global__ void composite_kernel(CompositeArgs a) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_pixels;
          i += (int64_t)gridDim.x * blockDim.x) {
         float dep[kMaxLayers];
         int idx[kMaxLayers];
+        int live = 0;
         for (int l = 0; l < a.n; ++l) {
             dep[l] = a.depth[l][i];
             idx[l] = l;
+            live += dep[l] < __builtin_inff();
+        }
+        if (live == 0) {
+            a.out[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            continue;
         }
         for (int l = 1; l < a.n; ++l) {          // insertion sort, stable
             const float dv = dep[l];
@@ -1262,7 +1272,7 @@ __global__ void composite_kernel(CompositeArgs a) {
             idx[m + 1] = iv;
         }
         float Cr = 0.f, Cg = 0.f, Cb = 0.f, A = 0.f;
-        for (int l = 0; l < a.n; ++l) {
+        for (int l = 0; l < live; ++l) {         // the finite depths sort first
             const float4 c = a.rgba[idx[l]][i];
             const float T = 1.f - A;
             Cr = fmaf(T, c.x, Cr);

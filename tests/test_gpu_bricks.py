@@ -128,3 +128,35 @@ def test_bricks_full_size(ctx):
     px = pixel_list(sc.height, sc.width, 500, rng, hit_mask=whole[..., 3] > 0, n_hit=1500)
     rec = oracle.render_pixels(sc, px, ert_threshold=NO_TERMINATION)
     compare(comp[px[:, 1], px[:, 0]], None, rec, label="8-brick composite 1080p vs oracle (sampled)")
+
+
+@pytest.mark.parametrize("n_layers", [1, 3, 8, 16])
+def test_composite_order_ties_and_uncovered_layers(ctx, n_layers):
+    """isaac_composite on synthetic layers against its definition: per pixel the layers
+    with a finite depth in depth order (ties in layer order), combined front to back;
+    a layer whose depth is +inf is not read there (its colour may be anything), and a
+    pixel no layer covers is transparent black, exactly.  Ragged size (3 partial waves)."""
+    import torch
+    rng = np.random.default_rng(50 + n_layers)
+    h, w = 37, 61
+    depth = rng.choice([1.0, 2.0, 2.5, 3.0, 7.0], size=(n_layers, h, w)).astype(np.float32)   # ties
+    depth[rng.random((n_layers, h, w)) < 0.4] = np.inf
+    depth[:, :5, :] = np.inf                                   # rows no layer covers
+    a = rng.uniform(0.0, 0.6, size=(n_layers, h, w, 1)).astype(np.float32)
+    rgba = np.concatenate([rng.uniform(0.0, 1.0, size=(n_layers, h, w, 3)).astype(np.float32) * a, a], axis=-1)
+    rgba[np.isinf(depth)] = 5.0                                # garbage where a layer does not cover the pixel
+    d_rgba = [torch.from_numpy(np.ascontiguousarray(rgba[l])).cuda() for l in range(n_layers)]
+    d_dep = [torch.from_numpy(np.ascontiguousarray(depth[l])).cuda() for l in range(n_layers)]
+    out = torch.full((h, w, 4), np.nan, device="cuda")
+    ctx.composite([t.data_ptr() for t in d_rgba], [t.data_ptr() for t in d_dep], w, h, out.data_ptr())
+    got = out.cpu().numpy().astype(np.float64)
+    ref = np.zeros((h, w, 4))
+    for j in range(h):
+        for i in range(w):
+            order = sorted((float(depth[l, j, i]), l) for l in range(n_layers) if np.isfinite(depth[l, j, i]))
+            C = np.zeros(4)
+            for _, l in order:
+                C = C + (1.0 - C[3]) * rgba[l, j, i].astype(np.float64)
+            ref[j, i] = C
+    assert np.all(got[:5] == 0.0)
+    assert np.abs(got - ref).max() < 1e-6, np.abs(got - ref).max()
