@@ -569,10 +569,12 @@ isaac_status build_job(isaac_context* ctx, const isaac_render_desc& j, bool need
     dj.mode = j.mode;
     dj.sig = signature_of(dj);
     if (dj.mode == ISAAC_ISO) {
-        // iso jobs run their own one-lane kernel with the runtime source loop
+        // iso jobs run their own kernel with the runtime source loop: 8 lanes per
+        // ray when the size class asks for several, else one
         dj.sig = SIG_GENERIC;
         dj.waves_hint = 0;
-        set_tiles(dj, 1, 1);
+        dj.pool = 0;
+        set_tiles(dj, ts.lanes >= 8 ? 8 : 1, 1);
     }
     *n_active_out = n_act;
     return ISAAC_OK;

@@ -931,6 +931,41 @@ __device__ __forceinline__ void march_dispatch(const DevJob& J, const float4* __
 // lit by a headlight, 0.3 + 0.7 |cos| of the angle between the ray and the
 // central-difference gradient (half a voxel each side).  One lane per ray;
 // the source loop is uniform, so every source's buffer resource stays scalar.
+// The crossing of source s between scan points k - 1 and k, at fraction f of
+// the step: opaque, the source's table colour at its iso value lit by a
+// headlight from the central-difference gradient (half a voxel each side).
+// s must be wave-uniform (the source's buffer resource is scalar).
+template <int INTERP>
+__device__ __forceinline__ float4 iso_shade(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
+                                            int s, int k, float f) {
+    // no contraction: (k + 1/2) step - tp is rounded as written wherever this is inlined
+#pragma clang fp contract(off)
+    const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
+    const float step = (float)J.step;
+    const DevSource& S = J.src[s];
+    const float tp = ((float)(k - 1) + 0.5f) * step;
+    const float ts = fmaf(f, ((float)k + 0.5f) * step - tp, tp);
+    float q[3];
+    point_at(J, R, ts, q);
+    float g[3] = {0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) {           // one axis at a time keeps register use low
+        const float hx = a == 0 ? 0.5f : 0.f, hy = a == 1 ? 0.5f : 0.f, hz = a == 2 ? 0.5f : 0.f;
+        const float qp[3] = {q[0] + hx, q[1] + hy, q[2] + hz}, qm[3] = {q[0] - hx, q[1] - hy, q[2] - hz};
+        const float d = sample_source<INTERP>(S, dims, qp) - sample_source<INTERP>(S, dims, qm);
+        g[0] = a == 0 ? d : g[0];
+        g[1] = a == 1 ? d : g[1];
+        g[2] = a == 2 ? d : g[2];
+    }
+    const float gl = sqrtf(fmaf(g[0], g[0], fmaf(g[1], g[1], g[2] * g[2])));
+    const float cosine = gl > 0.f ? fabsf(fmaf(g[0], R.d[0], fmaf(g[1], R.d[1], g[2] * R.d[2]))) / gl : 1.f;
+    const float light = fmaf(0.7f, fminf(cosine, 1.f), 0.3f);
+    const float4 c = classify(s_tf + s * kTfRows, S.iso);
+    return make_float4(c.x * light, c.y * light, c.z * light, 1.f);
+}
+
+// One lane per ray: scan points in order, every source at each, until the
+// first crossing.
 template <int INTERP>
 __device__ __forceinline__ void march_iso(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                           float4& out, int& count) {
@@ -957,29 +992,61 @@ __device__ __forceinline__ void march_iso(const DevJob& J, const float4* __restr
     out = make_float4(0.f, 0.f, 0.f, 0.f);
     count = n;
     // shade, one source at a time over the lanes whose surface it is
-    for (int s = 0; s < J.n_src; ++s) {
-        if (hit != s) continue;
-        const DevSource& S = J.src[s];
-        const float tp = ((float)(k - 1) + 0.5f) * step;
-        const float ts = fmaf(f, ((float)k + 0.5f) * step - tp, tp);
-        float q[3];
-        point_at(J, R, ts, q);
-        float g[3] = {0.f, 0.f, 0.f};
-#pragma unroll 1
-        for (int a = 0; a < 3; ++a) {           // one axis at a time keeps register use low
-            const float hx = a == 0 ? 0.5f : 0.f, hy = a == 1 ? 0.5f : 0.f, hz = a == 2 ? 0.5f : 0.f;
-            const float qp[3] = {q[0] + hx, q[1] + hy, q[2] + hz}, qm[3] = {q[0] - hx, q[1] - hy, q[2] - hz};
-            const float d = sample_source<INTERP>(S, dims, qp) - sample_source<INTERP>(S, dims, qm);
-            g[0] = a == 0 ? d : g[0];
-            g[1] = a == 1 ? d : g[1];
-            g[2] = a == 2 ? d : g[2];
+    for (int s = 0; s < J.n_src; ++s)
+        if (hit == s) out = iso_shade<INTERP>(J, s_tf, R, s, k, f);
+}
+
+// G lanes per ray: lane g takes scan point k0 + g of each row of G points; its
+// predecessor's values come from lane g - 1 (lane 0: the last point of the row
+// before), so every lane tests its own pair of consecutive points at once and
+// the ray's crossing is the first lane (then the first source in index order)
+// that sees one: the point, source and fraction the one-lane loop finds, with
+// the same arithmetic, in a fraction of its dependent steps.  The crossing's
+// lane shades, and passes colour and count to the group's first lane.
+template <int INTERP, int G>
+__device__ __forceinline__ void march_iso_lanes(const DevJob& J, const float4* __restrict__ s_tf,
+                                                const RaySetup& R, int lane, float4& out, int& count) {
+    const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
+    const float step = (float)J.step;
+    const int g = lane & (G - 1), base = lane & ~(G - 1);
+    constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull);
+    float carry[kMaxSources] = {};              // values at the last point of the previous row
+    int sel = -1, my_s = -1, k = R.kb;
+    float my_f = 0.f;
+    for (int k0 = R.kb;; k0 += G) {
+        k = k0 + g;
+        const bool valid = k < R.ke;
+        float p[3];
+        point_at(J, R, ((float)(valid ? k : R.ke - 1) + 0.5f) * step, p);
+        for (int s = 0; s < J.n_src; ++s) {
+            const DevSource& S = J.src[s];
+            const float x = sample_source<INTERP>(S, dims, p);
+            float prev = __shfl(x, base + ((g + G - 1) & (G - 1)), 64);
+            if (g == 0) prev = carry[s];
+            if (my_s < 0 && valid && k > R.kb && ((prev >= S.iso) != (x >= S.iso))) {
+                my_s = s;
+                my_f = (S.iso - prev) / (x - prev);
+            }
+            carry[s] = __shfl(x, base + G - 1, 64);
         }
-        const float gl = sqrtf(fmaf(g[0], g[0], fmaf(g[1], g[1], g[2] * g[2])));
-        const float cosine = gl > 0.f ? fabsf(fmaf(g[0], R.d[0], fmaf(g[1], R.d[1], g[2] * R.d[2]))) / gl : 1.f;
-        const float light = fmaf(0.7f, fminf(cosine, 1.f), 0.3f);
-        const float4 c = classify(s_tf + s * kTfRows, S.iso);
-        out = make_float4(c.x * light, c.y * light, c.z * light, 1.f);
+        const unsigned long long bits = (__builtin_amdgcn_ballot_w64(my_s >= 0) >> base) & kGroupMask;
+        if (bits) {
+            sel = (int)__builtin_ctzll(bits);
+            count = k0 + sel - R.kb + 1;
+            break;
+        }
+        if (k0 + G >= R.ke) {
+            count = R.ke - R.kb;
+            break;
+        }
     }
+    // shade one source at a time: the source must be the same on every active lane
+    // (its buffer resource is read as wave-uniform), whatever surface each ray found
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int s = 0; s < J.n_src; ++s)
+        if (g == sel && my_s == s) c = iso_shade<INTERP>(J, s_tf, R, s, k, my_f);
+    const int src = base + (sel >= 0 ? sel : 0);
+    out = make_float4(__shfl(c.x, src, 64), __shfl(c.y, src, 64), __shfl(c.z, src, 64), __shfl(c.w, src, 64));
 }
 
 __device__ __forceinline__ int find_job(const DevJob* __restrict__ jobs, int n_jobs, int tile) {
@@ -1073,9 +1140,12 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
         int count = 0;
         if (hit) {
-            if constexpr (SIGK == -2) {
+            if constexpr (SIGK == -2 && G == 1) {
                 if (J.interp) march_iso<1>(J, s_tf, R, c, count);
                 else march_iso<0>(J, s_tf, R, c, count);
+            } else if constexpr (SIGK == -2) {
+                if (J.interp) march_iso_lanes<1, G>(J, s_tf, R, lane, c, count);
+                else march_iso_lanes<0, G>(J, s_tf, R, lane, c, count);
             } else if constexpr (SIGK < 0) {
                 if (J.interp) march_dispatch<1, U, G, (W > 0)>(J, s_tf, R, lane, c, count);
                 else march_dispatch<0, U, G, (W > 0)>(J, s_tf, R, lane, c, count);
@@ -1596,7 +1666,7 @@ KernelFn pick_specialized(int unroll, int lanes, int hint) {
 }
 
 KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
-    if (mode == 1) return raycast_kernel<1, 1, 0, -2>;
+    if (mode == 1) return lanes >= 8 ? raycast_kernel<1, 8, 0, -2> : raycast_kernel<1, 1, 0, -2>;
     switch (sig) {
     case SIG_F32x1: return pick_specialized<SIG_F32x1>(unroll, lanes, hint);
     case SIG_PIC3_F32: return pick_specialized<SIG_PIC3_F32>(unroll, lanes, hint);

@@ -131,14 +131,46 @@ def test_iso_rejects_bricks(ctx):
     del vol
 
 
+def _with_shape(ctx, sc, shape):
+    """Render sc with `shape` as its size class's tile shape; restores the previous one."""
+    from paper_1611_09048_amd import autotune
+    cls = autotune.size_class(sc.width, sc.height)
+    old = ctx.get_tile_shape(cls)
+    try:
+        ctx.set_tile_shape(cls, *shape)
+        return render(ctx, sc)
+    finally:
+        ctx.set_tile_shape(cls, *old)
+
+
+@pytest.mark.parametrize("interpolation", [1, 0])
+@pytest.mark.parametrize("isos", [(0.6, 0.5, 0.55), (None, 0.45, None), (0.2, None, 0.9)])
+def test_iso_lanes_equal_one_lane(ctx, interpolation, isos):
+    """Several lanes per ray (8: the size class asks for 16) find the same crossing, source,
+    fraction and count as one lane per ray, bit for bit: every lane tests its own pair of
+    consecutive scan points and the first one wins.  Two clip planes, ragged image."""
+    sc = iso_scene(n=40, width=131, height=97, isos=isos, direction=(-0.4, -0.2, 0.9),
+                   interpolation=interpolation)
+    one_img, one_cnt = _with_shape(ctx, sc, (8, 2, 1, 1, 0, 0))
+    lanes_img, lanes_cnt = _with_shape(ctx, sc, (4, 1, 1, 16, 0, 0))
+    assert np.array_equal(one_img, lanes_img) and np.array_equal(one_cnt, lanes_cnt)
+    assert (lanes_img[:, 3] == 1.0).sum() > 100 or isos == (None, None, None)
+
+
 def test_iso_full_size_sampled(ctx):
     """The iso-surface form of the 256^3 1080p benchmark scene (density surface at 1.0, |E| at
-    0.2, B without a surface) in its launch configuration; sampled pixels, hit pixels included."""
+    0.2, B without a surface) in its launch configuration (the benchmark's tuned tile shape, so
+    8 lanes per ray); sampled pixels, hit pixels included."""
+    import os
+    from paper_1611_09048_amd import autotune
     from parity import pixel_list
     sc = configs.pic3()
     sc = sc.with_(mode="iso", sources=[dataclasses.replace(s, iso=v) for s, v in
                                        zip(sc.sources, (1.0, 0.2, float("nan")))])
-    img, cnt = render(ctx, sc)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = autotune.load_cache(os.path.join(root, "paper_1611_09048_amd", "tuned_gfx950.json"))
+    shape = cache[autotune.cache_key("gfx950", str(autotune.size_class(sc.width, sc.height)), "pic3:f32")]
+    img, cnt = _with_shape(ctx, sc, shape)
     img = img.reshape(sc.height, sc.width, 4)
     cnt = cnt.reshape(sc.height, sc.width)
     rng = np.random.default_rng(5)
