@@ -222,8 +222,9 @@ typedef struct {
  * visits each under trilinear interpolation) exceed 4 per voxel, or with
  * ISAAC_DERIVE, and at most 4 of its sources are active, the call first
  * evaluates every active source's functor chain once per voxel (guards
- * included) into a library-owned FP32 buffer of 4 bytes per voxel and source,
- * kept per volume until it is redefined, and the ray loop reads that buffer.
+ * included) into a library-owned FP32 buffer of 4 bytes per voxel and source
+ * (plus up to two padding layers per axis), kept per volume until it is
+ * redefined, and the ray loop reads that buffer.
  * The image is the same bit for bit.  ISAAC_DIRECT never derives.  Serving
  * calls (isaac_submit*) never derive. */
 isaac_status isaac_render(isaac_context* ctx, const isaac_render_desc* jobs, int n_jobs, unsigned flags);

@@ -377,13 +377,13 @@ bool finite3(const double v[3]) { return std::isfinite(v[0]) && std::isfinite(v[
 // Which compile-time specialized loop (if any) fits the job's active sources.
 int32_t signature_of(const DevJob& dj) {
     if (dj.n_src == 3) {
-        // three FP32 scalars interleaved in one buffer (a derived volume)
+        // the three sources of one derived volume in the (y, z)-paired layout, in order
         const DevSource* d = dj.src;
         bool il = true;
         for (int s = 0; s < 3; ++s)
             il = il && d[s].f_dim == 1 && d[s].dtype == DT_F32 && d[s].n_ops == 0 && d[s].base[0] == d[0].base[0] &&
                  d[s].num_records[0] == d[0].num_records[0] && d[s].comp_off[0] == d[0].comp_off[0] + 4 * s &&
-                 d[s].guard >= 1 && d[s].stride[0] == 12 && d[s].stride[1] == d[0].stride[1] &&
+                 d[s].guard >= 1 && d[s].layout == 1 && d[s].stride[0] == 48 && d[s].stride[1] == d[0].stride[1] &&
                  d[s].stride[2] == d[0].stride[2] && d[s].stride[1] < (1 << 23) && d[s].stride[2] < (1 << 23);
         if (il) return SIG_IL3;
     }
@@ -877,7 +877,13 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
             if (comp_of[s] >= 0) comp_of[s] = nd++;
         if (nd == 0 || nd > kMaxDerived || !benefit) continue;
         const int64_t ex = v.dims[0] + 2 * g, ey = v.dims[1] + 2 * g, ez = v.dims[2] + 2 * g;
-        const size_t bytes = (size_t)ex * ey * ez * nd * sizeof(float);
+        // three sources: the (y, z)-paired layout (stored y and z shifted by gp, an even
+        // number of layers at least g, so that index parity is the stored parity)
+        const bool paired = nd == 3;
+        const int gp = g + (g & 1);
+        const int64_t ny2 = (ey - g + gp + 1) / 2, nz2 = (ez - g + gp + 1) / 2;
+        const size_t bytes = paired ? (size_t)ex * ny2 * nz2 * 4 * nd * sizeof(float)
+                                    : (size_t)ex * ey * ez * nd * sizeof(float);
         if (bytes >= ((size_t)1 << 31)) continue;
         if (!force && est < 4.0 * (double)(ex * ey * ez)) continue;
         if (v.derived_bytes != bytes) {
@@ -901,6 +907,10 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
         da.ext[0] = (int)ex;
         da.ext[1] = (int)ey;
         da.ext[2] = (int)ez;
+        da.paired = paired ? 1 : 0;
+        da.gp = gp;
+        da.ny2 = (int)ny2;
+        da.nz2 = (int)nz2;
         da.dst = static_cast<float*>(v.derived);
         for (int i = 0; i < n; ++i) {
             if (jobs[i].volume_id != vid) continue;
@@ -944,8 +954,18 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
         const int dsig = signature_of(probe);
         int rc = launch_derive(da, dsig == SIG_IL3 ? (int)SIG_GENERIC : dsig, stream);
         if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "derive launch: %s", hipGetErrorString((hipError_t)rc));
-        const int32_t sx = 4 * nd, sy = (int32_t)(sx * ex), sz = (int32_t)(sy * ey);
-        const int32_t o0 = g * (sx + sy + sz);
+        int32_t sx, sy, sz, o0;
+        if (paired) {
+            sx = 16 * nd;                           // 4 records per x
+            sy = (int32_t)(sx * ex);                // per stored y pair
+            sz = (int32_t)(sy * ny2);               // per stored z pair
+            o0 = g * sx + (gp / 2) * (sy + sz);     // voxel (0, 0, 0): stored (g, gp, gp)
+        } else {
+            sx = 4 * nd;
+            sy = (int32_t)(sx * ex);
+            sz = (int32_t)(sy * ey);
+            o0 = g * (sx + sy + sz);
+        }
         for (int i = 0; i < n; ++i) {
             if (jobs[i].volume_id != vid) continue;
             DevJob& dj = djs[i];
@@ -959,6 +979,7 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
                 d.num_records[0] = (uint32_t)bytes;
                 d.comp_off[0] = o0 + 4 * comp_of[dj.src_index[k]];
                 d.packed = 1;
+                d.layout = paired ? 1 : 0;
                 d.stride[0] = sx;
                 d.stride[1] = sy;
                 d.stride[2] = sz;
@@ -1030,6 +1051,7 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
             std::memcpy(d.comp_off, f.comp_off, sizeof d.comp_off);
             std::memcpy(d.stride, f.stride, sizeof d.stride);
             d.packed = f.packed;
+            d.layout = f.layout;
             d.f_dim = 1;
             d.dtype = DT_F32;
             d.n_ops = 0;

@@ -49,7 +49,7 @@ enum Signature : int32_t {
     SIG_PIC3_F32 = 2,     // FP32 scalar, FP32 3-vector, FP32 3-vector
     SIG_PIC3_F16 = 3,     // the same in FP16
     SIG_PIC3_BF16 = 4,    // the same in BF16
-    SIG_IL3 = 5,          // three FP32 scalars interleaved in one buffer (a derived volume)
+    SIG_IL3 = 5,          // a three-source derived volume (DevSource layout 1)
 };
 
 struct DevSource {
@@ -57,7 +57,14 @@ struct DevSource {
     uint32_t num_records[4];  // per component: bytes readable from base (buffer-resource range)
     int32_t comp_off[4];   // byte offset of component c of voxel (0,0,0) from base[c]
     int32_t packed;        // components adjacent in memory: one range (index 0), one wide load
-    int32_t stride[3];     // byte strides along x, y, z
+    // 0: voxel (x, y, z) at x stride[0] + y stride[1] + z stride[2] + comp_off.
+    // 1 (derived volumes): (y, z) pairs interleaved: records of rs = stride[0] / 4
+    // bytes, voxel at (z >> 1) stride[2] + (y >> 1) stride[1] + x stride[0] +
+    // ((z & 1) 2 + (y & 1)) rs + comp_off (arithmetic shifts: guard index -1
+    // lies in pair -1), so the 2 x 2 (y, z) neighbours of a voxel share its
+    // 4 rs bytes.
+    int32_t layout;
+    int32_t stride[3];     // byte strides along x, y, z (layout 1: x, y pair, z pair)
     int32_t f_dim;
     int32_t dtype;
     int32_t guard;         // >= 1: corners may reach index -1 and N; 0: clamp to the border
@@ -154,7 +161,11 @@ constexpr int kMaxDevices = 64;
 int noalloc_scratch(int device, void** ptr);
 
 // Derived volume: the functor-chain output of up to 4 sources at every voxel
-// of [-g, N-1+g]^3, interleaved (n floats per voxel, x fastest).
+// of [-g, N-1+g]^3, interleaved (n floats per voxel).  paired = 0: x fastest,
+// then y, then z.  paired = 1 (DevSource layout 1): rows of x records for each
+// pair of (y, z) pairs, the 4 records of a (y, z) quad adjacent; stored y and
+// z indices are index + gp (gp = g rounded up to even, so a stored pair holds
+// an even index and the next one), ny2 x nz2 pairs.
 constexpr int kMaxDerived = 4;
 constexpr int kMaxKeepSets = 4;
 struct DeriveArgs {
@@ -162,6 +173,9 @@ struct DeriveArgs {
     int n;                        // sources (components per voxel)
     int g;                        // guard layers covered
     int ext[3];                   // N + 2g per axis
+    int paired;                   // 1: (y, z)-paired layout
+    int gp;                       // g rounded up to even (paired)
+    int ny2, nz2;                 // stored y and z pairs (paired)
     float org[3];                 // index of voxel (0,0,0) in the clip planes' space
     // Voxels no kept scan point can read are skipped: a voxel is derived if,
     // for at least one set, it lies within 3 voxels of every plane's kept side

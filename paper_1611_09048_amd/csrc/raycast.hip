@@ -364,6 +364,14 @@ __device__ __forceinline__ bool setup_ray(const DevJob& J, int px, int py, RaySe
     return true;
 }
 
+// Byte offset of voxel (x, y, z) from comp_off in either layout (DevSource).
+__device__ __forceinline__ int voxel_offset(const DevSource& S, int x, int y, int z) {
+    if (S.layout == 1)
+        return (z >> 1) * S.stride[2] + (y >> 1) * S.stride[1] + x * S.stride[0] +
+               ((z & 1) * 2 + (y & 1)) * (S.stride[0] >> 2);
+    return x * S.stride[0] + y * S.stride[1] + z * S.stride[2];
+}
+
 // One source at position p: nearest cell, or trilinear over the chain
 // outputs of the 8 surrounding voxels (chain per fetched voxel, then blend).
 template <int INTERP>
@@ -372,7 +380,7 @@ __device__ __forceinline__ float sample_source(const DevSource& S, const int dim
         const int qx = clampi((int)floorf(p[0]), 0, dims[0] - 1);
         const int qy = clampi((int)floorf(p[1]), 0, dims[1] - 1);
         const int qz = clampi((int)floorf(p[2]), 0, dims[2] - 1);
-        const int off[1] = {qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2]};
+        const int off[1] = {voxel_offset(S, qx, qy, qz)};
         float v[1][4], r[1];
         fetch<1>(S, off, v);
         run_chain<1>(S, v, r);
@@ -392,11 +400,24 @@ __device__ __forceinline__ float sample_source(const DevSource& S, const int dim
             i1[a] = clampi(i1[a], 0, dims[a] - 1);
         }
     }
-    const int x0 = i0[0] * S.stride[0], x1 = i1[0] * S.stride[0];
-    const int y0 = i0[1] * S.stride[1], y1 = i1[1] * S.stride[1];
-    const int z0 = i0[2] * S.stride[2], z1 = i1[2] * S.stride[2];
-    const int off[8] = {x0 + y0 + z0, x1 + y0 + z0, x0 + y1 + z0, x1 + y1 + z0,
-                        x0 + y0 + z1, x1 + y0 + z1, x0 + y1 + z1, x1 + y1 + z1};
+    int off[8];
+    if (S.layout == 1) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            off[c] = voxel_offset(S, c & 1 ? i1[0] : i0[0], c & 2 ? i1[1] : i0[1], c & 4 ? i1[2] : i0[2]);
+    } else {
+        const int x0 = i0[0] * S.stride[0], x1 = i1[0] * S.stride[0];
+        const int y0 = i0[1] * S.stride[1], y1 = i1[1] * S.stride[1];
+        const int z0 = i0[2] * S.stride[2], z1 = i1[2] * S.stride[2];
+        off[0] = x0 + y0 + z0;
+        off[1] = x1 + y0 + z0;
+        off[2] = x0 + y1 + z0;
+        off[3] = x1 + y1 + z0;
+        off[4] = x0 + y0 + z1;
+        off[5] = x1 + y0 + z1;
+        off[6] = x0 + y1 + z1;
+        off[7] = x1 + y1 + z1;
+    }
     float v[8][4], c[8];
     fetch<8>(S, off, v);
     run_chain<8>(S, v, c);
@@ -426,7 +447,8 @@ template <int INTERP, bool CLAMP = true>
 __device__ __forceinline__ void corner_offsets(const DevSource& S, const int dims[3], const int (&i0)[3],
                                                int (&off)[INTERP ? 8 : 1]) {
     if (INTERP == 0) {
-        off[0] = __mul24(i0[0], S.stride[0]) + __mul24(i0[1], S.stride[1]) + __mul24(i0[2], S.stride[2]);
+        if (S.layout == 1) off[0] = voxel_offset(S, i0[0], i0[1], i0[2]);
+        else off[0] = __mul24(i0[0], S.stride[0]) + __mul24(i0[1], S.stride[1]) + __mul24(i0[2], S.stride[2]);
         return;
     }
     int a0[3], a1[3];
@@ -438,6 +460,13 @@ __device__ __forceinline__ void corner_offsets(const DevSource& S, const int dim
             a0[a] = clampi(a0[a], 0, dims[a] - 1);
             a1[a] = clampi(a1[a], 0, dims[a] - 1);
         }
+    }
+    if (S.layout == 1) {
+        // a derived volume in the (y, z)-paired layout (not a hot path: those run fetch_il3)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            off[c] = voxel_offset(S, c & 1 ? a1[0] : a0[0], c & 2 ? a1[1] : a0[1], c & 4 ? a1[2] : a0[2]);
+        return;
     }
     const int x0 = __mul24(a0[0], S.stride[0]), x1 = __mul24(a1[0], S.stride[0]);
     const int y0 = __mul24(a0[1], S.stride[1]), y1 = __mul24(a1[1], S.stride[1]);
@@ -469,35 +498,41 @@ __device__ __forceinline__ void fetch_kind(const DevSource& S, const int (&off)[
     }
 }
 
-// The 8 trilinear corners (or the nearest cell) of an interleaved derived
-// volume: two per-lane base offsets (z0 and z1 planes) and the wave-uniform
-// x/y corner steps in the loads' scalar offset, so a corner costs no vector
-// address arithmetic.  Same corner order as corner_offsets.
+// The 8 trilinear corners (or the nearest cell) of a three-source derived
+// volume (layout 1: (y, z) pairs of 12-byte records), same corner order as
+// corner_offsets.  The x + 1 corners are 48 bytes on (the loads' scalar
+// offset); the y + 1 and z + 1 corners lie in the same pair or the next one
+// depending on the parity of the index.  A wave's gathers of one corner touch
+// fewer cache lines on oblique rays than in an x-fastest layout.
 template <int INTERP>
 __device__ __forceinline__ void fetch_il3(const DevSource& S, const int (&i0)[3], float (&v)[INTERP ? 8 : 1][4]) {
     const __amdgpu_buffer_rsrc_t r = make_rsrc(S.base[0], S.num_records[0]);
     const int sx = __builtin_amdgcn_readfirstlane(S.stride[0]);
     const int sy = __builtin_amdgcn_readfirstlane(S.stride[1]);
     const int sz = __builtin_amdgcn_readfirstlane(S.stride[2]);
-    const int b0 = __mul24(i0[0], sx) + __mul24(i0[1], sy) + __mul24(i0[2], sz) + S.comp_off[0];
     auto ld3 = [&](int vo, int so, float (&d)[4]) {
         d[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
         d[1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo + 4, so, 0));
         d[2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo + 8, so, 0));
         d[3] = 0.f;
     };
+    const int yl = i0[1] & 1, zl = i0[2] & 1;
+    const int b0 = __mul24(i0[2] >> 1, sz) + __mul24(i0[1] >> 1, sy) + __mul24(i0[0], sx) + __mul24(zl, 24) +
+                   __mul24(yl, 12) + S.comp_off[0];
     if constexpr (INTERP == 0) {
         ld3(b0, 0, v[0]);
     } else {
-        const int b1 = b0 + sz;
+        const int oy = __mul24(yl, sy - 24) + 12;   // y + 1: same pair (+12) or the next one
+        const int oz = __mul24(zl, sz - 48) + 24;   // z + 1: same pair (+24) or the next one
+        const int b2 = b0 + oy, b4 = b0 + oz, b6 = b4 + oy;
         ld3(b0, 0, v[0]);
         ld3(b0, sx, v[1]);
-        ld3(b0, sy, v[2]);
-        ld3(b0, sx + sy, v[3]);
-        ld3(b1, 0, v[4]);
-        ld3(b1, sx, v[5]);
-        ld3(b1, sy, v[6]);
-        ld3(b1, sx + sy, v[7]);
+        ld3(b2, 0, v[2]);
+        ld3(b2, sx, v[3]);
+        ld3(b4, 0, v[4]);
+        ld3(b4, sx, v[5]);
+        ld3(b6, 0, v[6]);
+        ld3(b6, sx, v[7]);
     }
 }
 
@@ -1396,25 +1431,43 @@ __global__ void encode_rgba8_kernel(EncodeArgs a) {
 
 // Derived volume: every voxel's chain output per source, computed once with
 // the same fetch and chain code as the ray loop (so the values are the ones
-// the loop would compute at that voxel, bit for bit).  Blocks of 256 threads
-// cover consecutive voxels of one z-slice (x fastest): reads and the
-// interleaved writes are coalesced.  SIG > 0: the sources have that
-// signature's compile-time kinds; SIG = 0: any sources.
-template <int SIG>
-__device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int yi, int zi0, int nz) {
-    constexpr int kZ = 4;                      // z-slices per thread: their loads are in flight together
+// the loop would compute at that voxel, bit for bit).  A thread takes 4 voxels
+// with their loads in flight together: one (x, y) in 4 consecutive z-slices
+// (x-fastest layout), or, in the paired layout, both y parities of one stored
+// y pair at one x and one z parity in 2 consecutive stored z pairs (its two
+// records of a pair are adjacent; lanes alternate the z parity, then step x).
+// A wave's stores are one contiguous run (x-fastest) or 64 adjacent record
+// pairs, and its reads of a source cover whole runs of 64 or 2 x 32 x.
+// SIG > 0: the sources have that signature's compile-time kinds; SIG = 0: any
+// sources.
+template <int SIG, bool PAIRED>
+__device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int slot, int yi, int zi0, int nz) {
+    constexpr int kZ = 4;
     const int ex = a.ext[0], ey = a.ext[1];
-    const int x = xi - a.g, y = yi - a.g;
+    const int x = xi - a.g;
+    int vy[kZ], vz[kZ];                        // volume indices of the 4 voxels
+    int64_t rec[kZ];                           // their records (float index / n)
     bool need[kZ];
 #pragma unroll
     for (int j = 0; j < kZ; ++j) {
-        const int z = zi0 + j - a.g;
-        need[j] = j < nz;
+        if (PAIRED) {
+            // slot: the z parity; j: y parity (j & 1) in stored z pair zi0 + (j >> 1)
+            const int zp = zi0 + (j >> 1);
+            vy[j] = 2 * yi + (j & 1) - a.gp;
+            vz[j] = 2 * zp + slot - a.gp;
+            need[j] = (j >> 1) < nz && vy[j] >= -a.g && vy[j] < ey - a.g && vz[j] >= -a.g && vz[j] < a.ext[2] - a.g;
+            rec[j] = (((int64_t)zp * a.ny2 + yi) * ex + xi) * 4 + 2 * slot + (j & 1);
+        } else {
+            vy[j] = yi - a.g;
+            vz[j] = zi0 + j - a.g;
+            need[j] = j < nz;
+            rec[j] = ((int64_t)(zi0 + j) * ey + yi) * ex + xi;
+        }
         if (need[j] && a.n_sets > 0) {
             // a kept scan point reads voxel centres less than one voxel away per axis
             // (1.5 for the iso-surface gradient), i.e. within 1.5 sqrt(3) < 3 of it
             // along any unit normal
-            const float c[3] = {a.org[0] + x + 0.5f, a.org[1] + y + 0.5f, a.org[2] + z + 0.5f};
+            const float c[3] = {a.org[0] + x + 0.5f, a.org[1] + vy[j] + 0.5f, a.org[2] + vz[j] + 0.5f};
             bool any = false;
             for (int k = 0; k < a.n_sets && !any; ++k) {
                 bool inside = true;
@@ -1427,19 +1480,27 @@ __device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int y
             need[j] = any;
         }
     }
-    bool any_needed = false;
+    int first = -1;
 #pragma unroll
-    for (int j = 0; j < kZ; ++j) any_needed = any_needed || need[j];
-    if (!any_needed) return;
+    for (int j = kZ - 1; j >= 0; --j)
+        if (need[j]) first = j;
+    if (first < 0) return;
+    // a voxel that is not needed reads the first needed one's address (harmless, never stored)
+    int ry[kZ], rz[kZ];
+#pragma unroll
+    for (int j = 0; j < kZ; ++j) {
+        ry[j] = need[j] ? vy[j] : vy[first];
+        rz[j] = need[j] ? vz[j] : vz[first];
+    }
     // a source without guard layers never has them read: its guard cells hold the border values
-    auto offset = [&](const DevSource& S, int z) {
+    auto offset = [&](const DevSource& S, int y, int z) {
         const int qx = S.guard < 1 ? clampi(x, 0, ex - 2 * a.g - 1) : x;
         const int qy = S.guard < 1 ? clampi(y, 0, ey - 2 * a.g - 1) : y;
         const int qz = S.guard < 1 ? clampi(z, 0, a.ext[2] - 2 * a.g - 1) : z;
         return qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2];
     };
     auto store = [&](int j, float o0, float o1, float o2, float o3) {
-        float* d = a.dst + ((int64_t)(zi0 + j) * ey + yi) * ex * a.n + (int64_t)xi * a.n;
+        float* d = a.dst + rec[j] * a.n;
         switch (a.n) {
         case 4: *reinterpret_cast<float4*>(d) = make_float4(o0, o1, o2, o3); break;
         case 3: d[0] = o0; d[1] = o1; d[2] = o2; break;
@@ -1452,12 +1513,11 @@ __device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int y
 #pragma unroll
         for (int j = 0; j < kZ; ++j) {
             if (!need[j]) continue;
-            const int z = zi0 + j - a.g;
             float v[kMaxDerived][1][4];
 #pragma unroll
             for (int s = 0; s < kMaxDerived; ++s) {
                 if (s < a.n) {
-                    const int off[1] = {offset(a.src[s], z)};
+                    const int off[1] = {offset(a.src[s], ry[j], rz[j])};
                     fetch<1>(a.src[s], off, v[s]);
                 }
             }
@@ -1476,21 +1536,20 @@ __device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int y
         float out[kZ][kMaxDerived];
         constexpr int K0 = SigKinds<SIG>::k0, K1 = SigKinds<SIG>::k1, K2 = SigKinds<SIG>::k2;
         float v0[kZ][4], v1[kZ][4], v2[kZ][4];
-        // every load of the kZ voxels first (a skipped voxel reads its neighbour's address harmlessly)
+        // every load of the 4 voxels first
 #pragma unroll
         for (int j = 0; j < kZ; ++j) {
-            const int z = zi0 + (need[j] ? j : 0) - a.g;
             float t[1][4];
-            const int o0[1] = {offset(a.src[0], z)};
+            const int o0[1] = {offset(a.src[0], ry[j], rz[j])};
             fetch_kind<K0, 1>(a.src[0], o0, t);
             for (int c = 0; c < 4; ++c) v0[j][c] = t[0][c];
             if constexpr (K1 != K_NONE) {
-                const int o1[1] = {offset(a.src[1], z)};
+                const int o1[1] = {offset(a.src[1], ry[j], rz[j])};
                 fetch_kind<K1, 1>(a.src[1], o1, t);
                 for (int c = 0; c < 4; ++c) v1[j][c] = t[0][c];
             }
             if constexpr (K2 != K_NONE) {
-                const int o2[1] = {offset(a.src[2], z)};
+                const int o2[1] = {offset(a.src[2], ry[j], rz[j])};
                 fetch_kind<K2, 1>(a.src[2], o2, t);
                 for (int c = 0; c < 4; ++c) v2[j][c] = t[0][c];
             }
@@ -1520,22 +1579,22 @@ __device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int y
     }
 }
 
-// Derived volume: every voxel's chain output per source, computed once with
-// the same fetch and chain code as the ray loop (so the values are the ones
-// the loop would compute at that voxel, bit for bit).  Blocks of 256 threads
-// cover consecutive voxels of a z-slice (x fastest: reads and the interleaved
-// writes are coalesced); each thread takes 4 slices with their loads in
-// flight together.  SIG > 0: the sources have that signature's compile-time
-// kinds; SIG = 0: any sources.
-template <int SIG>
+// Blocks of 256 threads cover consecutive threads of consecutive rows (y, or
+// stored y pairs of 2 ex threads) of one slab (4 z-slices, or 2 stored z
+// pairs); grid z strides over the slabs.
+template <int SIG, bool PAIRED>
 __global__ __launch_bounds__(256) void derive_kernel(DeriveArgs a) {
-    const int ex = a.ext[0], ey = a.ext[1];
+    const int ex = a.ext[0];
+    const int row = PAIRED ? 2 * ex : ex;
+    const int rows = PAIRED ? a.ny2 : a.ext[1];
     const int idx = (int)(blockIdx.x * 256 + threadIdx.x);
-    if (idx >= ex * ey) return;
-    const int yi = idx / ex;
-    const int xi = idx - yi * ex;
-    for (int zi0 = 4 * (int)blockIdx.z; zi0 < a.ext[2]; zi0 += 4 * (int)gridDim.z)
-        derive_voxels<SIG>(a, xi, yi, zi0, min(4, a.ext[2] - zi0));
+    if (idx >= row * rows) return;
+    const int yi = idx / row;
+    const int r = idx - yi * row;
+    const int xi = PAIRED ? r >> 1 : r, slot = PAIRED ? r & 1 : 0;
+    const int nzs = PAIRED ? a.nz2 : a.ext[2], per = PAIRED ? 2 : 4;
+    for (int zi0 = per * (int)blockIdx.z; zi0 < nzs; zi0 += per * (int)gridDim.z)
+        derive_voxels<SIG, PAIRED>(a, xi, slot, yi, zi0, min(per, nzs - zi0));
 }
 
 // Ray setup of every pixel of each job's screen rectangle, one lane per ray,
@@ -1819,19 +1878,27 @@ int launch_encode_rgba8(const float* rgba, int64_t n_pixels, const float* bg, un
     return hipGetLastError();
 }
 
+template <bool PAIRED>
+void (*derive_variant(int sig))(DeriveArgs) {
+    switch (sig) {
+    case SIG_F32x1: return derive_kernel<SIG_F32x1, PAIRED>;
+    case SIG_PIC3_F32: return derive_kernel<SIG_PIC3_F32, PAIRED>;
+    case SIG_PIC3_F16: return derive_kernel<SIG_PIC3_F16, PAIRED>;
+    case SIG_PIC3_BF16: return derive_kernel<SIG_PIC3_BF16, PAIRED>;
+    default: return derive_kernel<SIG_GENERIC, PAIRED>;
+    }
+}
+
 int launch_derive(const DeriveArgs& a, int sig, void* stream) {
     if (a.ext[0] <= 0 || a.ext[1] <= 0 || a.ext[2] <= 0) return hipSuccess;
-    const int64_t slice = (int64_t)a.ext[0] * a.ext[1];
+    if (a.paired && (a.gp < a.g || (a.gp & 1) || 2 * a.ny2 < a.ext[1] - a.g + a.gp ||
+                     2 * a.nz2 < a.ext[2] - a.g + a.gp))
+        return hipErrorInvalidValue;
+    const int64_t slice = (int64_t)a.ext[0] * (a.paired ? 2 * (int64_t)a.ny2 : a.ext[1]);
     if (slice > (1LL << 30)) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((slice + 255) / 256), 1, (unsigned)std::min((a.ext[2] + 3) / 4, 65535));
-    void (*k)(DeriveArgs) = derive_kernel<SIG_GENERIC>;
-    switch (sig) {
-    case SIG_F32x1: k = derive_kernel<SIG_F32x1>; break;
-    case SIG_PIC3_F32: k = derive_kernel<SIG_PIC3_F32>; break;
-    case SIG_PIC3_F16: k = derive_kernel<SIG_PIC3_F16>; break;
-    case SIG_PIC3_BF16: k = derive_kernel<SIG_PIC3_BF16>; break;
-    default: break;
-    }
+    const int slabs = a.paired ? (a.nz2 + 1) / 2 : (a.ext[2] + 3) / 4;
+    const dim3 grid((unsigned)((slice + 255) / 256), 1, (unsigned)std::min(slabs, 65535));
+    void (*k)(DeriveArgs) = a.paired ? derive_variant<true>(sig) : derive_variant<false>(sig);
     hipLaunchKernelGGL(k, grid, dim3(256), 0, (hipStream_t)stream, a);
     return hipGetLastError();
 }

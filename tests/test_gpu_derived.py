@@ -82,6 +82,24 @@ def test_derived_with_disabled_source_layouts_and_guardless(ctx):
     assert_same(a, b, "middle source disabled")
 
 
+def test_paired_layout_odd_extents(ctx):
+    """Three-source derived volumes interleave (y, z) pairs: odd and unequal extents
+    (padding pairs), nearest and trilinear, iso mode, and sources without guard
+    layers (the generic loop reads the paired volume with the border clamp)."""
+    base = configs.pic3(dims=(37, 35, 33), width=96, height=80, direction=(-0.7, 0.5, 0.5))
+    for interp in (1, 0):
+        a, b = both(ctx, base.with_(interpolation=interp), vid=20 + interp)
+        assert_same(a, b, f"odd extents interp={interp}")
+    iso = base.with_(mode="iso", sources=[dataclasses.replace(s, iso=v) for s, v in
+                                          zip(base.sources, (1.0, 0.2, float("nan")))])
+    a, b = both(ctx, iso, vid=22)
+    assert_same(a, b, "odd extents iso")
+    bare = [make_source(s.name, s.values[1:-1, 1:-1, 1:-1].astype(np.float32), guard=0, chain=s.chain,
+                        weight=s.weight, tf=s.tf) for s in base.sources]
+    a, b = both(ctx, base.with_(sources=bare), vid=23)
+    assert_same(a, b, "odd extents, no guard layers")
+
+
 def test_derived_iso_mode(ctx):
     sc = configs.pic3(n=40, width=128, height=96)
     sc = sc.with_(mode="iso", sources=[dataclasses.replace(s, iso=v) for s, v in
