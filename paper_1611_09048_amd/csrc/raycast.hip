@@ -1463,22 +1463,36 @@ __device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int s
             need[j] = j < nz;
             rec[j] = ((int64_t)(zi0 + j) * ey + yi) * ex + xi;
         }
-        if (need[j] && a.n_sets > 0) {
-            // a kept scan point reads voxel centres less than one voxel away per axis
-            // (1.5 for the iso-surface gradient), i.e. within 1.5 sqrt(3) < 3 of it
-            // along any unit normal
-            const float c[3] = {a.org[0] + x + 0.5f, a.org[1] + vy[j] + 0.5f, a.org[2] + vz[j] + 0.5f};
-            bool any = false;
-            for (int k = 0; k < a.n_sets && !any; ++k) {
-                bool inside = true;
-                for (int p = 0; p < a.n_planes[k]; ++p) {
-                    const float* pl = a.planes[k][p];
-                    inside = inside && pl[0] * c[0] + pl[1] * c[1] + pl[2] * c[2] + pl[3] >= -3.f;
-                }
-                any = inside;
-            }
-            need[j] = any;
+    }
+    // The clip test: this latency-bound pass waits on each wave's chain of
+    // dependent scalar reads before its loads, so planes are outermost (each read
+    // once for the 4 voxels), not one read per voxel and plane.
+    if (a.n_sets > 0) {
+        // a kept scan point reads voxel centres less than one voxel away per axis
+        // (1.5 for the iso-surface gradient), i.e. within 1.5 sqrt(3) < 3 of it
+        // along any unit normal
+        bool any[kZ] = {false, false, false, false};
+        auto test = [&](const float* pl, bool use, bool (&inside)[kZ]) {
+            const float n0 = pl[0], n1 = pl[1], n2 = pl[2], n3 = pl[3];
+            const float base = n0 * (a.org[0] + x + 0.5f);
+#pragma unroll
+            for (int j = 0; j < kZ; ++j)
+                inside[j] = inside[j] &&
+                            (!use || base + n1 * (a.org[1] + vy[j] + 0.5f) + n2 * (a.org[2] + vz[j] + 0.5f) + n3 >= -3.f);
+        };
+        for (int k = 0; k < a.n_sets; ++k) {
+            bool inside[kZ] = {true, true, true, true};
+            const int np = a.n_planes[k];
+            // the first two planes of a set are read whether used or not (the arrays
+            // hold kMaxClip planes), so their loads go out together with the count
+            test(a.planes[k][0], np > 0, inside);
+            test(a.planes[k][1], np > 1, inside);
+            for (int p = 2; p < np; ++p) test(a.planes[k][p], true, inside);
+#pragma unroll
+            for (int j = 0; j < kZ; ++j) any[j] = any[j] || inside[j];
         }
+#pragma unroll
+        for (int j = 0; j < kZ; ++j) need[j] = need[j] && any[j];
     }
     int first = -1;
 #pragma unroll
