@@ -272,7 +272,9 @@ isaac_status isaac_composite(isaac_context* ctx, const float* const* rgba, const
  * source's functor chain is evaluated once per voxel now (guards included),
  * into the library-owned derived volume of 4 bytes per voxel and source, and
  * every later render or served request of the volume, whatever its clip
- * planes and enabled sources, reads those values instead of the sources.
+ * planes and enabled sources, reads those values instead of the sources (with
+ * three sources, whose values are stored for the three-source loop, an
+ * iso-surface job or one with fewer active sources reads the sources).
  * Images are the same bit for bit.  The sources must be persistent and at
  * most 4; their update callbacks are called once here and still before each
  * render.  The caller must not change the sources' memory while the volume is

@@ -377,15 +377,16 @@ bool finite3(const double v[3]) { return std::isfinite(v[0]) && std::isfinite(v[
 // Which compile-time specialized loop (if any) fits the job's active sources.
 int32_t signature_of(const DevJob& dj) {
     if (dj.n_src == 3) {
-        // the three sources of one derived volume in the (y, z)-paired layout, in order
+        // the three sources of one derived volume (either layout), in order
         const DevSource* d = dj.src;
         bool il = true;
         for (int s = 0; s < 3; ++s)
             il = il && d[s].f_dim == 1 && d[s].dtype == DT_F32 && d[s].n_ops == 0 && d[s].base[0] == d[0].base[0] &&
                  d[s].num_records[0] == d[0].num_records[0] && d[s].comp_off[0] == d[0].comp_off[0] + 4 * s &&
-                 d[s].guard >= 1 && d[s].layout == 1 && d[s].stride[0] == 48 && d[s].stride[1] == d[0].stride[1] &&
-                 d[s].stride[2] == d[0].stride[2] && d[s].stride[1] < (1 << 23) && d[s].stride[2] < (1 << 23);
-        if (il) return SIG_IL3;
+                 d[s].guard >= 1 && d[s].layout == d[0].layout && d[s].stride[0] == (d[s].layout ? 48 : 12) &&
+                 d[s].stride[1] == d[0].stride[1] && d[s].stride[2] == d[0].stride[2] && d[s].stride[1] < (1 << 23) &&
+                 d[s].stride[2] < (1 << 23);
+        if (il) return d[0].layout ? SIG_IL3P : SIG_IL3;
     }
     int kinds[kMaxSources];
     for (int s = 0; s < dj.n_src; ++s) {
@@ -877,13 +878,70 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
             if (comp_of[s] >= 0) comp_of[s] = nd++;
         if (nd == 0 || nd > kMaxDerived || !benefit) continue;
         const int64_t ex = v.dims[0] + 2 * g, ey = v.dims[1] + 2 * g, ez = v.dims[2] + 2 * g;
-        // three sources: the (y, z)-paired layout (stored y and z shifted by gp, an even
-        // number of layers at least g, so that index parity is the stored parity)
-        const bool paired = nd == 3;
+        // The derived sources in either layout: x fastest, or (three sources) the (y, z)
+        // pairs, stored y and z shifted by gp, an even number of layers at least g, so
+        // that index parity is the stored parity.
         const int gp = g + (g & 1);
         const int64_t ny2 = (ey - g + gp + 1) / 2, nz2 = (ez - g + gp + 1) / 2;
-        const size_t bytes = paired ? (size_t)ex * ny2 * nz2 * 4 * nd * sizeof(float)
-                                    : (size_t)ex * ey * ez * nd * sizeof(float);
+        struct Layout {
+            bool paired;
+            size_t bytes;
+            int64_t sx, sy, sz, o0;
+        };
+        auto layout_of = [&](bool p) {
+            Layout L;
+            L.paired = p;
+            if (p) {
+                L.sx = 16 * nd;                         // 4 records per x
+                L.sy = L.sx * ex;                       // per stored y pair
+                L.sz = L.sy * ny2;                      // per stored z pair
+                L.o0 = g * L.sx + (gp / 2) * (L.sy + L.sz);   // voxel (0, 0, 0): stored (g, gp, gp)
+                L.bytes = (size_t)ex * ny2 * nz2 * 4 * nd * sizeof(float);
+            } else {
+                L.sx = 4 * nd;
+                L.sy = L.sx * ex;
+                L.sz = L.sy * ey;
+                L.o0 = g * (L.sx + L.sy + L.sz);
+                L.bytes = (size_t)ex * ey * ez * nd * sizeof(float);
+            }
+            return L;
+        };
+        auto describe = [&](DevJob& dj, const Layout& L, void* base) {
+            for (int k = 0; k < dj.n_src; ++k) {
+                DevSource& d = dj.src[k];
+                const int guard = d.guard;
+                std::memset(d.base, 0, sizeof d.base);
+                std::memset(d.num_records, 0, sizeof d.num_records);
+                std::memset(d.comp_off, 0, sizeof d.comp_off);
+                d.base[0] = reinterpret_cast<uint64_t>(base);
+                d.num_records[0] = (uint32_t)L.bytes;
+                d.comp_off[0] = (int32_t)(L.o0 + 4 * comp_of[dj.src_index[k]]);
+                d.packed = 1;
+                d.layout = L.paired ? 1 : 0;
+                d.stride[0] = (int32_t)L.sx;
+                d.stride[1] = (int32_t)L.sy;
+                d.stride[2] = (int32_t)L.sz;
+                d.f_dim = 1;
+                d.dtype = DT_F32;
+                d.guard = guard;
+                d.n_ops = 0;
+            }
+        };
+        // The paired layout only when every job of the volume in this call then runs the
+        // three-source loop, its only reader (calls with iso or fewer-source jobs keep x
+        // fastest; a volume frozen in pairs is read directly by such jobs later).
+        bool paired = nd == 3;
+        if (paired) {
+            const Layout P = layout_of(true);
+            for (int i = 0; i < n && paired; ++i) {
+                if (jobs[i].volume_id != vid) continue;
+                DevJob t = djs[i];
+                describe(t, P, reinterpret_cast<void*>((uintptr_t)256));
+                paired = t.mode != ISAAC_ISO && signature_of(t) == SIG_IL3P;
+            }
+        }
+        const Layout L = layout_of(paired);
+        const size_t bytes = L.bytes;
         if (bytes >= ((size_t)1 << 31)) continue;
         if (!force && est < 4.0 * (double)(ex * ey * ez)) continue;
         if (v.derived_bytes != bytes) {
@@ -952,42 +1010,12 @@ isaac_status derive_volumes(isaac_context* ctx, const isaac_render_desc* jobs, s
         probe.n_src = nd;
         for (int k = 0; k < nd; ++k) probe.src[k] = da.src[k];
         const int dsig = signature_of(probe);
-        int rc = launch_derive(da, dsig == SIG_IL3 ? (int)SIG_GENERIC : dsig, stream);
+        int rc = launch_derive(da, dsig == SIG_IL3 || dsig == SIG_IL3P ? (int)SIG_GENERIC : dsig, stream);
         if (rc != hipSuccess) return set_err(ctx, ISAAC_ERR_DEVICE, "derive launch: %s", hipGetErrorString((hipError_t)rc));
-        int32_t sx, sy, sz, o0;
-        if (paired) {
-            sx = 16 * nd;                           // 4 records per x
-            sy = (int32_t)(sx * ex);                // per stored y pair
-            sz = (int32_t)(sy * ny2);               // per stored z pair
-            o0 = g * sx + (gp / 2) * (sy + sz);     // voxel (0, 0, 0): stored (g, gp, gp)
-        } else {
-            sx = 4 * nd;
-            sy = (int32_t)(sx * ex);
-            sz = (int32_t)(sy * ey);
-            o0 = g * (sx + sy + sz);
-        }
         for (int i = 0; i < n; ++i) {
             if (jobs[i].volume_id != vid) continue;
             DevJob& dj = djs[i];
-            for (int k = 0; k < dj.n_src; ++k) {
-                DevSource& d = dj.src[k];
-                const int guard = d.guard;
-                std::memset(d.base, 0, sizeof d.base);
-                std::memset(d.num_records, 0, sizeof d.num_records);
-                std::memset(d.comp_off, 0, sizeof d.comp_off);
-                d.base[0] = reinterpret_cast<uint64_t>(v.derived);
-                d.num_records[0] = (uint32_t)bytes;
-                d.comp_off[0] = o0 + 4 * comp_of[dj.src_index[k]];
-                d.packed = 1;
-                d.layout = paired ? 1 : 0;
-                d.stride[0] = sx;
-                d.stride[1] = sy;
-                d.stride[2] = sz;
-                d.f_dim = 1;
-                d.dtype = DT_F32;
-                d.guard = guard;
-                d.n_ops = 0;
-            }
+            describe(dj, L, v.derived);
             if (dj.mode != ISAAC_ISO) dj.sig = signature_of(dj);
         }
     }
@@ -1038,14 +1066,18 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
             }
         }
     }
-    // frozen volumes: every job reads the derived values (render and serving calls alike)
+    // frozen volumes: every job reads the derived values (render and serving calls
+    // alike), except, on a volume frozen in (y, z) pairs, a job that would not run
+    // the three-source loop (the layout's only reader): it reads the unchanged
+    // sources directly
     for (int i = 0; i < n; ++i) {
         const Volume& v = ctx->volumes[jobs[i].volume_id];
         if (!v.frozen || (flags & ISAAC_DIRECT)) continue;
         DevJob& dj = djs[i];
-        for (int k = 0; k < dj.n_src; ++k) {
-            const DevSource& f = v.frozen_src[dj.src_index[k]];
-            DevSource& d = dj.src[k];
+        DevJob t = dj;
+        for (int k = 0; k < t.n_src; ++k) {
+            const DevSource& f = v.frozen_src[t.src_index[k]];
+            DevSource& d = t.src[k];
             std::memcpy(d.base, f.base, sizeof d.base);
             std::memcpy(d.num_records, f.num_records, sizeof d.num_records);
             std::memcpy(d.comp_off, f.comp_off, sizeof d.comp_off);
@@ -1056,7 +1088,9 @@ isaac_status render_impl(isaac_context* ctx, const isaac_render_desc* jobs, int 
             d.dtype = DT_F32;
             d.n_ops = 0;
         }
-        if (dj.mode != ISAAC_ISO) dj.sig = signature_of(dj);
+        if (t.mode != ISAAC_ISO) t.sig = signature_of(t);
+        const bool paired = t.n_src > 0 && t.src[0].layout == 1;
+        if (!paired || (t.mode != ISAAC_ISO && t.sig == SIG_IL3P)) dj = t;
     }
     if (allow_derive && !(flags & ISAAC_DIRECT)) {
         st = derive_volumes(ctx, jobs, djs, (flags & ISAAC_DERIVE) != 0, stream);

@@ -49,7 +49,8 @@ enum Signature : int32_t {
     SIG_PIC3_F32 = 2,     // FP32 scalar, FP32 3-vector, FP32 3-vector
     SIG_PIC3_F16 = 3,     // the same in FP16
     SIG_PIC3_BF16 = 4,    // the same in BF16
-    SIG_IL3 = 5,          // a three-source derived volume (DevSource layout 1)
+    SIG_IL3 = 5,          // a three-source derived volume, x fastest (DevSource layout 0)
+    SIG_IL3P = 6,         // a three-source derived volume in (y, z) pairs (DevSource layout 1)
 };
 
 struct DevSource {
@@ -58,11 +59,11 @@ struct DevSource {
     int32_t comp_off[4];   // byte offset of component c of voxel (0,0,0) from base[c]
     int32_t packed;        // components adjacent in memory: one range (index 0), one wide load
     // 0: voxel (x, y, z) at x stride[0] + y stride[1] + z stride[2] + comp_off.
-    // 1 (derived volumes): (y, z) pairs interleaved: records of rs = stride[0] / 4
-    // bytes, voxel at (z >> 1) stride[2] + (y >> 1) stride[1] + x stride[0] +
-    // ((z & 1) 2 + (y & 1)) rs + comp_off (arithmetic shifts: guard index -1
-    // lies in pair -1), so the 2 x 2 (y, z) neighbours of a voxel share its
-    // 4 rs bytes.
+    // 1 (three-source derived volumes, read only by the SIG_IL3P loop): (y, z)
+    // pairs interleaved, records of 12 bytes, voxel at (z >> 1) stride[2] +
+    // (y >> 1) stride[1] + x stride[0] + ((z & 1) 2 + (y & 1)) 12 + comp_off
+    // (arithmetic shifts: guard index -1 lies in pair -1), so the 2 x 2 (y, z)
+    // neighbours of a voxel share its 48 bytes.
     int32_t layout;
     int32_t stride[3];     // byte strides along x, y, z (layout 1: x, y pair, z pair)
     int32_t f_dim;

@@ -364,14 +364,6 @@ __device__ __forceinline__ bool setup_ray(const DevJob& J, int px, int py, RaySe
     return true;
 }
 
-// Byte offset of voxel (x, y, z) from comp_off in either layout (DevSource).
-__device__ __forceinline__ int voxel_offset(const DevSource& S, int x, int y, int z) {
-    if (S.layout == 1)
-        return (z >> 1) * S.stride[2] + (y >> 1) * S.stride[1] + x * S.stride[0] +
-               ((z & 1) * 2 + (y & 1)) * (S.stride[0] >> 2);
-    return x * S.stride[0] + y * S.stride[1] + z * S.stride[2];
-}
-
 // One source at position p: nearest cell, or trilinear over the chain
 // outputs of the 8 surrounding voxels (chain per fetched voxel, then blend).
 template <int INTERP>
@@ -380,7 +372,7 @@ __device__ __forceinline__ float sample_source(const DevSource& S, const int dim
         const int qx = clampi((int)floorf(p[0]), 0, dims[0] - 1);
         const int qy = clampi((int)floorf(p[1]), 0, dims[1] - 1);
         const int qz = clampi((int)floorf(p[2]), 0, dims[2] - 1);
-        const int off[1] = {voxel_offset(S, qx, qy, qz)};
+        const int off[1] = {qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2]};
         float v[1][4], r[1];
         fetch<1>(S, off, v);
         run_chain<1>(S, v, r);
@@ -400,24 +392,11 @@ __device__ __forceinline__ float sample_source(const DevSource& S, const int dim
             i1[a] = clampi(i1[a], 0, dims[a] - 1);
         }
     }
-    int off[8];
-    if (S.layout == 1) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-            off[c] = voxel_offset(S, c & 1 ? i1[0] : i0[0], c & 2 ? i1[1] : i0[1], c & 4 ? i1[2] : i0[2]);
-    } else {
-        const int x0 = i0[0] * S.stride[0], x1 = i1[0] * S.stride[0];
-        const int y0 = i0[1] * S.stride[1], y1 = i1[1] * S.stride[1];
-        const int z0 = i0[2] * S.stride[2], z1 = i1[2] * S.stride[2];
-        off[0] = x0 + y0 + z0;
-        off[1] = x1 + y0 + z0;
-        off[2] = x0 + y1 + z0;
-        off[3] = x1 + y1 + z0;
-        off[4] = x0 + y0 + z1;
-        off[5] = x1 + y0 + z1;
-        off[6] = x0 + y1 + z1;
-        off[7] = x1 + y1 + z1;
-    }
+    const int x0 = i0[0] * S.stride[0], x1 = i1[0] * S.stride[0];
+    const int y0 = i0[1] * S.stride[1], y1 = i1[1] * S.stride[1];
+    const int z0 = i0[2] * S.stride[2], z1 = i1[2] * S.stride[2];
+    const int off[8] = {x0 + y0 + z0, x1 + y0 + z0, x0 + y1 + z0, x1 + y1 + z0,
+                        x0 + y0 + z1, x1 + y0 + z1, x0 + y1 + z1, x1 + y1 + z1};
     float v[8][4], c[8];
     fetch<8>(S, off, v);
     run_chain<8>(S, v, c);
@@ -447,8 +426,7 @@ template <int INTERP, bool CLAMP = true>
 __device__ __forceinline__ void corner_offsets(const DevSource& S, const int dims[3], const int (&i0)[3],
                                                int (&off)[INTERP ? 8 : 1]) {
     if (INTERP == 0) {
-        if (S.layout == 1) off[0] = voxel_offset(S, i0[0], i0[1], i0[2]);
-        else off[0] = __mul24(i0[0], S.stride[0]) + __mul24(i0[1], S.stride[1]) + __mul24(i0[2], S.stride[2]);
+        off[0] = __mul24(i0[0], S.stride[0]) + __mul24(i0[1], S.stride[1]) + __mul24(i0[2], S.stride[2]);
         return;
     }
     int a0[3], a1[3];
@@ -460,13 +438,6 @@ __device__ __forceinline__ void corner_offsets(const DevSource& S, const int dim
             a0[a] = clampi(a0[a], 0, dims[a] - 1);
             a1[a] = clampi(a1[a], 0, dims[a] - 1);
         }
-    }
-    if (S.layout == 1) {
-        // a derived volume in the (y, z)-paired layout (not a hot path: those run fetch_il3)
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-            off[c] = voxel_offset(S, c & 1 ? a1[0] : a0[0], c & 2 ? a1[1] : a0[1], c & 4 ? a1[2] : a0[2]);
-        return;
     }
     const int x0 = __mul24(a0[0], S.stride[0]), x1 = __mul24(a1[0], S.stride[0]);
     const int y0 = __mul24(a0[1], S.stride[1]), y1 = __mul24(a1[1], S.stride[1]);
@@ -499,12 +470,14 @@ __device__ __forceinline__ void fetch_kind(const DevSource& S, const int (&off)[
 }
 
 // The 8 trilinear corners (or the nearest cell) of a three-source derived
-// volume (layout 1: (y, z) pairs of 12-byte records), same corner order as
-// corner_offsets.  The x + 1 corners are 48 bytes on (the loads' scalar
-// offset); the y + 1 and z + 1 corners lie in the same pair or the next one
-// depending on the parity of the index.  A wave's gathers of one corner touch
-// fewer cache lines on oblique rays than in an x-fastest layout.
-template <int INTERP>
+// volume, 12-byte records, same corner order as corner_offsets.
+// PAIRED (layout 1, (y, z) pairs): the x + 1 corners are 48 bytes on (the
+// loads' scalar offset); the y + 1 and z + 1 corners lie in the same pair or
+// the next one depending on the parity of the index.  A wave's gathers of one
+// corner touch fewer cache lines on oblique rays than in the x-fastest layout.
+// Layout 0 (x fastest): two per-lane base offsets (z0 and z1 planes) and the
+// wave-uniform x/y corner steps in the scalar offset.
+template <int INTERP, bool PAIRED>
 __device__ __forceinline__ void fetch_il3(const DevSource& S, const int (&i0)[3], float (&v)[INTERP ? 8 : 1][4]) {
     const __amdgpu_buffer_rsrc_t r = make_rsrc(S.base[0], S.num_records[0]);
     const int sx = __builtin_amdgcn_readfirstlane(S.stride[0]);
@@ -516,23 +489,40 @@ __device__ __forceinline__ void fetch_il3(const DevSource& S, const int (&i0)[3]
         d[2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo + 8, so, 0));
         d[3] = 0.f;
     };
-    const int yl = i0[1] & 1, zl = i0[2] & 1;
-    const int b0 = __mul24(i0[2] >> 1, sz) + __mul24(i0[1] >> 1, sy) + __mul24(i0[0], sx) + __mul24(zl, 24) +
-                   __mul24(yl, 12) + S.comp_off[0];
-    if constexpr (INTERP == 0) {
-        ld3(b0, 0, v[0]);
+    if constexpr (PAIRED) {
+        const int yl = i0[1] & 1, zl = i0[2] & 1;
+        const int b0 = __mul24(i0[2] >> 1, sz) + __mul24(i0[1] >> 1, sy) + __mul24(i0[0], sx) + __mul24(zl, 24) +
+                       __mul24(yl, 12) + S.comp_off[0];
+        if constexpr (INTERP == 0) {
+            ld3(b0, 0, v[0]);
+        } else {
+            const int oy = __mul24(yl, sy - 24) + 12;   // y + 1: same pair (+12) or the next one
+            const int oz = __mul24(zl, sz - 48) + 24;   // z + 1: same pair (+24) or the next one
+            const int b2 = b0 + oy, b4 = b0 + oz, b6 = b4 + oy;
+            ld3(b0, 0, v[0]);
+            ld3(b0, sx, v[1]);
+            ld3(b2, 0, v[2]);
+            ld3(b2, sx, v[3]);
+            ld3(b4, 0, v[4]);
+            ld3(b4, sx, v[5]);
+            ld3(b6, 0, v[6]);
+            ld3(b6, sx, v[7]);
+        }
     } else {
-        const int oy = __mul24(yl, sy - 24) + 12;   // y + 1: same pair (+12) or the next one
-        const int oz = __mul24(zl, sz - 48) + 24;   // z + 1: same pair (+24) or the next one
-        const int b2 = b0 + oy, b4 = b0 + oz, b6 = b4 + oy;
-        ld3(b0, 0, v[0]);
-        ld3(b0, sx, v[1]);
-        ld3(b2, 0, v[2]);
-        ld3(b2, sx, v[3]);
-        ld3(b4, 0, v[4]);
-        ld3(b4, sx, v[5]);
-        ld3(b6, 0, v[6]);
-        ld3(b6, sx, v[7]);
+        const int b0 = __mul24(i0[0], sx) + __mul24(i0[1], sy) + __mul24(i0[2], sz) + S.comp_off[0];
+        if constexpr (INTERP == 0) {
+            ld3(b0, 0, v[0]);
+        } else {
+            const int b1 = b0 + sz;
+            ld3(b0, 0, v[0]);
+            ld3(b0, sx, v[1]);
+            ld3(b0, sy, v[2]);
+            ld3(b0, sx + sy, v[3]);
+            ld3(b1, 0, v[4]);
+            ld3(b1, sx, v[5]);
+            ld3(b1, sy, v[6]);
+            ld3(b1, sx + sy, v[7]);
+        }
     }
 }
 
@@ -597,6 +587,7 @@ template <> struct SigKinds<SIG_PIC3_F32> { static constexpr int k0 = K_F32x1, k
 template <> struct SigKinds<SIG_PIC3_F16> { static constexpr int k0 = K_F16x1, k1 = K_F16x3, k2 = K_F16x3; };
 template <> struct SigKinds<SIG_PIC3_BF16> { static constexpr int k0 = K_BF16x1, k1 = K_BF16x3, k2 = K_BF16x3; };
 template <> struct SigKinds<SIG_IL3> { static constexpr int k0 = K_F32x1, k1 = K_F32x1, k2 = K_F32x1; };
+template <> struct SigKinds<SIG_IL3P> { static constexpr int k0 = K_F32x1, k1 = K_F32x1, k2 = K_F32x1; };
 
 // PS (per source): load, chain, blend and classify one source before the
 // next one's loads; fewer live registers (more resident waves) at the cost of
@@ -646,12 +637,12 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
             E[u][1] = fmaf(wa, cl.y, E[u][1]);
             E[u][2] = fmaf(wa, cl.z, E[u][2]);
         };
-        if constexpr (SIG == SIG_IL3) {
+        if constexpr (SIG == SIG_IL3 || SIG == SIG_IL3P) {
             // the three chain outputs of a voxel are adjacent: one 12-byte load per corner
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 float v[NV][4];
-                fetch_il3<INTERP>(J.src[0], i0[u], v);
+                fetch_il3<INTERP, SIG == SIG_IL3P>(J.src[0], i0[u], v);
 #pragma unroll
                 for (int s = 0; s < 3; ++s) {
                     float c[NV];
@@ -888,7 +879,7 @@ __device__ __forceinline__ void il3_mix(const DevJob& J, const float4* __restric
     mix_finish(S, E);
 }
 
-template <int INTERP, int G>
+template <int INTERP, int G, bool PAIRED>
 __device__ __forceinline__ void march_lanes_il3(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                                 int lane, float4& out, int& count) {
     constexpr int NV = INTERP ? 8 : 1;
@@ -896,14 +887,14 @@ __device__ __forceinline__ void march_lanes_il3(const DevJob& J, const float4* _
     int i0[3];
     float w[3], v[NV][4];
     il3_locate<INTERP>(J, R, R.kb + g, i0, w);
-    fetch_il3<INTERP>(J.src[0], i0, v);
+    fetch_il3<INTERP, PAIRED>(J.src[0], i0, v);
     RayAccum acc = {0.f, 0.f, 0.f, 0.f, 0};
     for (int k0 = R.kb;; k0 += G) {
         // the next row's loads (clamped to the last scan point: always in bounds)
         int i0n[3];
         float wn[3], vn[NV][4];
         il3_locate<INTERP>(J, R, k0 + G + g, i0n, wn);
-        fetch_il3<INTERP>(J.src[0], i0n, vn);
+        fetch_il3<INTERP, PAIRED>(J.src[0], i0n, vn);
         const bool valid = k0 + g < R.ke;
         float E[3], S;
         il3_mix<NV>(J, s_tf, v, w, E, S);
@@ -942,7 +933,8 @@ template <int INTERP, int U, int G, int SIG, bool PS>
 __device__ __forceinline__ void march_sig(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                           int lane, float4& out, int& count) {
     if constexpr (G == 1) march_seq<INTERP, (SIG == SIG_GENERIC ? 1 : U), SIG, PS>(J, s_tf, R, out, count);
-    else if constexpr (SIG == SIG_IL3 && !PS) march_lanes_il3<INTERP, G>(J, s_tf, R, lane, out, count);
+    else if constexpr ((SIG == SIG_IL3 || SIG == SIG_IL3P) && !PS)
+        march_lanes_il3<INTERP, G, SIG == SIG_IL3P>(J, s_tf, R, lane, out, count);
     else march_lanes<INTERP, G, SIG, PS>(J, s_tf, R, lane, out, count);
 }
 
@@ -955,6 +947,7 @@ __device__ __forceinline__ void march_dispatch(const DevJob& J, const float4* __
     case SIG_PIC3_F16: march_sig<INTERP, U, G, SIG_PIC3_F16, PS>(J, s_tf, R, lane, out, count); break;
     case SIG_PIC3_BF16: march_sig<INTERP, U, G, SIG_PIC3_BF16, PS>(J, s_tf, R, lane, out, count); break;
     case SIG_IL3: march_sig<INTERP, U, G, SIG_IL3, PS>(J, s_tf, R, lane, out, count); break;
+    case SIG_IL3P: march_sig<INTERP, U, G, SIG_IL3P, PS>(J, s_tf, R, lane, out, count); break;
     default: march_sig<INTERP, U, G, SIG_GENERIC, PS>(J, s_tf, R, lane, out, count); break;
     }
 }
@@ -1257,6 +1250,7 @@ __device__ __forceinline__ bool pool_row(const DevJob& J, const float4* __restri
         case SIG_PIC3_F16: return lanes_row<INTERP, G, SIG_PIC3_F16, PS>(J, s_tf, R, lane, k0, acc);
         case SIG_PIC3_BF16: return lanes_row<INTERP, G, SIG_PIC3_BF16, PS>(J, s_tf, R, lane, k0, acc);
         case SIG_IL3: return lanes_row<INTERP, G, SIG_IL3, PS>(J, s_tf, R, lane, k0, acc);
+        case SIG_IL3P: return lanes_row<INTERP, G, SIG_IL3P, PS>(J, s_tf, R, lane, k0, acc);
         default: return lanes_row<INTERP, G, SIG_GENERIC, PS>(J, s_tf, R, lane, k0, acc);
         }
     }
@@ -1746,6 +1740,7 @@ KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
     case SIG_PIC3_F16: return pick_specialized<SIG_PIC3_F16>(unroll, lanes, hint);
     case SIG_PIC3_BF16: return pick_specialized<SIG_PIC3_BF16>(unroll, lanes, hint);
     case SIG_IL3: return pick_specialized<SIG_IL3>(unroll, lanes, hint);
+    case SIG_IL3P: return pick_specialized<SIG_IL3P>(unroll, lanes, hint);
     default:
         break;
     }
@@ -1809,6 +1804,7 @@ PoolFn pick_pool_kernel(int sig, int lanes, int hint) {
     case SIG_PIC3_F16: return pick_pool_specialized<SIG_PIC3_F16>(lanes, hint);
     case SIG_PIC3_BF16: return pick_pool_specialized<SIG_PIC3_BF16>(lanes, hint);
     case SIG_IL3: return pick_pool_specialized<SIG_IL3>(lanes, hint);
+    case SIG_IL3P: return pick_pool_specialized<SIG_IL3P>(lanes, hint);
     default: break;
     }
     switch (lanes) {

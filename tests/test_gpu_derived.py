@@ -83,9 +83,10 @@ def test_derived_with_disabled_source_layouts_and_guardless(ctx):
 
 
 def test_paired_layout_odd_extents(ctx):
-    """Three-source derived volumes interleave (y, z) pairs: odd and unequal extents
-    (padding pairs), nearest and trilinear, iso mode, and sources without guard
-    layers (the generic loop reads the paired volume with the border clamp)."""
+    """Three-source derived volumes of a call whose jobs all run the three-source
+    loop interleave (y, z) pairs: odd and unequal extents (padding pairs), nearest
+    and trilinear.  Iso jobs and sources without guard layers (read by other
+    loops) get the x-fastest layout; all equal the direct render."""
     base = configs.pic3(dims=(37, 35, 33), width=96, height=80, direction=(-0.7, 0.5, 0.5))
     for interp in (1, 0):
         a, b = both(ctx, base.with_(interpolation=interp), vid=20 + interp)
