@@ -698,7 +698,18 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
         if (dj.sig != la.sig) la.sig = -1;
     if (la.sig == SIG_GENERIC) la.sig = -1;
     la.mode = djs[0].mode;
-    if (la.mode == ISAAC_ISO) la.sig = -2;
+    if (la.mode == ISAAC_ISO) {
+        // the plain-source iso kernel when every source is a packed FP32 scalar without
+        // functors, with guard layers and x-fastest strides (derived volumes, plain scalars)
+        bool plain = true;
+        for (const DevJob& dj : djs)
+            for (int k = 0; k < dj.n_src; ++k) {
+                const DevSource& d = dj.src[k];
+                plain = plain && d.packed && d.dtype == DT_F32 && d.f_dim == 1 && d.n_ops == 0 && d.guard >= 1 &&
+                        d.layout == 0;
+            }
+        la.sig = plain ? -3 : -2;
+    }
     {
         size_t maxpix = 1;
         for (const DevJob& dj : djs) maxpix = std::max(maxpix, (size_t)dj.width * dj.height);

@@ -409,6 +409,53 @@ __device__ __forceinline__ float sample_source(const DevSource& S, const int dim
     return fmaf(w[2], c1 - c0, c0);
 }
 
+// A plain source (packed FP32 scalar, no functor, guard layers: a derived
+// component, or such a source itself) at position p: sample_source's loads
+// and arithmetic, without its run-time storage and chain handling (and so
+// without the registers they hold).
+template <int INTERP>
+__device__ __forceinline__ float sample_plain(const DevSource& S, const int dims[3], const float p[3]) {
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(S.base[0], S.num_records[0]);
+    const int o = S.comp_off[0];
+    if (INTERP == 0) {
+        const int qx = clampi((int)floorf(p[0]), 0, dims[0] - 1);
+        const int qy = clampi((int)floorf(p[1]), 0, dims[1] - 1);
+        const int qz = clampi((int)floorf(p[2]), 0, dims[2] - 1);
+        return ld_f32(r, qx * S.stride[0] + qy * S.stride[1] + qz * S.stride[2] + o);
+    }
+    int i0[3], i1[3];
+    float w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = p[a] - 0.5f;
+        const float fl = floorf(u);
+        w[a] = u - fl;
+        i0[a] = (int)fl;
+        i1[a] = i0[a] + 1;
+    }
+    const int x0 = i0[0] * S.stride[0], x1 = i1[0] * S.stride[0];
+    const int y0 = i0[1] * S.stride[1], y1 = i1[1] * S.stride[1];
+    const int z0 = i0[2] * S.stride[2], z1 = i1[2] * S.stride[2];
+    const int off[8] = {x0 + y0 + z0, x1 + y0 + z0, x0 + y1 + z0, x1 + y1 + z0,
+                        x0 + y0 + z1, x1 + y0 + z1, x0 + y1 + z1, x1 + y1 + z1};
+    float c[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = ld_f32(r, off[i] + o);
+    const float c00 = fmaf(w[0], c[1] - c[0], c[0]);
+    const float c10 = fmaf(w[0], c[3] - c[2], c[2]);
+    const float c01 = fmaf(w[0], c[5] - c[4], c[4]);
+    const float c11 = fmaf(w[0], c[7] - c[6], c[6]);
+    const float c0 = fmaf(w[1], c10 - c00, c00);
+    const float c1 = fmaf(w[1], c11 - c01, c01);
+    return fmaf(w[2], c1 - c0, c0);
+}
+
+template <int INTERP, bool PLAIN>
+__device__ __forceinline__ float sample_any(const DevSource& S, const int dims[3], const float p[3]) {
+    if constexpr (PLAIN) return sample_plain<INTERP>(S, dims, p);
+    else return sample_source<INTERP>(S, dims, p);
+}
+
 // Compile-time source kinds of the specialized scan-point loop.
 enum Kind : int { K_NONE = 0, K_F32x1 = 1, K_F32x3 = 2, K_F16x1 = 3, K_F16x3 = 4, K_BF16x1 = 5, K_BF16x3 = 6 };
 
@@ -963,7 +1010,7 @@ __device__ __forceinline__ void march_dispatch(const DevJob& J, const float4* __
 // the step: opaque, the source's table colour at its iso value lit by a
 // headlight from the central-difference gradient (half a voxel each side).
 // s must be wave-uniform (the source's buffer resource is scalar).
-template <int INTERP>
+template <int INTERP, bool PLAIN>
 __device__ __forceinline__ float4 iso_shade(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                             int s, int k, float f) {
     // no contraction: (k + 1/2) step - tp is rounded as written wherever this is inlined
@@ -980,7 +1027,7 @@ __device__ __forceinline__ float4 iso_shade(const DevJob& J, const float4* __res
     for (int a = 0; a < 3; ++a) {           // one axis at a time keeps register use low
         const float hx = a == 0 ? 0.5f : 0.f, hy = a == 1 ? 0.5f : 0.f, hz = a == 2 ? 0.5f : 0.f;
         const float qp[3] = {q[0] + hx, q[1] + hy, q[2] + hz}, qm[3] = {q[0] - hx, q[1] - hy, q[2] - hz};
-        const float d = sample_source<INTERP>(S, dims, qp) - sample_source<INTERP>(S, dims, qm);
+        const float d = sample_any<INTERP, PLAIN>(S, dims, qp) - sample_any<INTERP, PLAIN>(S, dims, qm);
         g[0] = a == 0 ? d : g[0];
         g[1] = a == 1 ? d : g[1];
         g[2] = a == 2 ? d : g[2];
@@ -994,7 +1041,7 @@ __device__ __forceinline__ float4 iso_shade(const DevJob& J, const float4* __res
 
 // One lane per ray: scan points in order, every source at each, until the
 // first crossing.
-template <int INTERP>
+template <int INTERP, bool PLAIN>
 __device__ __forceinline__ void march_iso(const DevJob& J, const float4* __restrict__ s_tf, const RaySetup& R,
                                           float4& out, int& count) {
     const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
@@ -1008,7 +1055,7 @@ __device__ __forceinline__ void march_iso(const DevJob& J, const float4* __restr
         ++n;
         for (int s = 0; s < J.n_src; ++s) {
             const DevSource& S = J.src[s];
-            const float x = sample_source<INTERP>(S, dims, p);
+            const float x = sample_any<INTERP, PLAIN>(S, dims, p);
             if (hit < 0 && k > R.kb && ((prev[s] >= S.iso) != (x >= S.iso))) {
                 hit = s;
                 f = (S.iso - prev[s]) / (x - prev[s]);
@@ -1021,7 +1068,7 @@ __device__ __forceinline__ void march_iso(const DevJob& J, const float4* __restr
     count = n;
     // shade, one source at a time over the lanes whose surface it is
     for (int s = 0; s < J.n_src; ++s)
-        if (hit == s) out = iso_shade<INTERP>(J, s_tf, R, s, k, f);
+        if (hit == s) out = iso_shade<INTERP, PLAIN>(J, s_tf, R, s, k, f);
 }
 
 // G lanes per ray: lane g takes scan point k0 + g of each row of G points; its
@@ -1031,7 +1078,7 @@ __device__ __forceinline__ void march_iso(const DevJob& J, const float4* __restr
 // that sees one: the point, source and fraction the one-lane loop finds, with
 // the same arithmetic, in a fraction of its dependent steps.  The crossing's
 // lane shades, and passes colour and count to the group's first lane.
-template <int INTERP, int G>
+template <int INTERP, int G, bool PLAIN>
 __device__ __forceinline__ void march_iso_lanes(const DevJob& J, const float4* __restrict__ s_tf,
                                                 const RaySetup& R, int lane, float4& out, int& count) {
     const int dims[3] = {J.dims[0], J.dims[1], J.dims[2]};
@@ -1048,7 +1095,7 @@ __device__ __forceinline__ void march_iso_lanes(const DevJob& J, const float4* _
         point_at(J, R, ((float)(valid ? k : R.ke - 1) + 0.5f) * step, p);
         for (int s = 0; s < J.n_src; ++s) {
             const DevSource& S = J.src[s];
-            const float x = sample_source<INTERP>(S, dims, p);
+            const float x = sample_any<INTERP, PLAIN>(S, dims, p);
             float prev = __shfl(x, base + ((g + G - 1) & (G - 1)), 64);
             if (g == 0) prev = carry[s];
             if (my_s < 0 && valid && k > R.kb && ((prev >= S.iso) != (x >= S.iso))) {
@@ -1072,7 +1119,7 @@ __device__ __forceinline__ void march_iso_lanes(const DevJob& J, const float4* _
     // (its buffer resource is read as wave-uniform), whatever surface each ray found
     float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int s = 0; s < J.n_src; ++s)
-        if (g == sel && my_s == s) c = iso_shade<INTERP>(J, s_tf, R, s, k, my_f);
+        if (g == sel && my_s == s) c = iso_shade<INTERP, PLAIN>(J, s_tf, R, s, k, my_f);
     const int src = base + (sel >= 0 ? sel : 0);
     out = make_float4(__shfl(c.x, src, 64), __shfl(c.y, src, 64), __shfl(c.z, src, 64), __shfl(c.w, src, 64));
 }
@@ -1105,7 +1152,8 @@ __device__ __forceinline__ bool pixel_of(const DevJob& J, int t, int lane, int w
 // resident waves per SIMD and evaluates the sources one after another.
 // SIGK >= 0: the kernel runs only that source signature (every job of the
 // launch has it); SIGK = -1: it dispatches on each job's signature; SIGK = -2:
-// iso-surface jobs.
+// iso-surface jobs; SIGK = -3: iso-surface jobs whose sources are all plain
+// (sample_plain).
 template <int U, int G, int W, int SIGK>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, 8)))
 void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ tf_pool, int* __restrict__ cursor,
@@ -1168,12 +1216,14 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
         int count = 0;
         if (hit) {
-            if constexpr (SIGK == -2 && G == 1) {
-                if (J.interp) march_iso<1>(J, s_tf, R, c, count);
-                else march_iso<0>(J, s_tf, R, c, count);
-            } else if constexpr (SIGK == -2) {
-                if (J.interp) march_iso_lanes<1, G>(J, s_tf, R, lane, c, count);
-                else march_iso_lanes<0, G>(J, s_tf, R, lane, c, count);
+            if constexpr ((SIGK == -2 || SIGK == -3) && G == 1) {
+                constexpr bool PL = SIGK == -3;
+                if (J.interp) march_iso<1, PL>(J, s_tf, R, c, count);
+                else march_iso<0, PL>(J, s_tf, R, c, count);
+            } else if constexpr (SIGK == -2 || SIGK == -3) {
+                constexpr bool PL = SIGK == -3;
+                if (J.interp) march_iso_lanes<1, G, PL>(J, s_tf, R, lane, c, count);
+                else march_iso_lanes<0, G, PL>(J, s_tf, R, lane, c, count);
             } else if constexpr (SIGK < 0) {
                 if (J.interp) march_dispatch<1, U, G, (W > 0)>(J, s_tf, R, lane, c, count);
                 else march_dispatch<0, U, G, (W > 0)>(J, s_tf, R, lane, c, count);
@@ -1733,7 +1783,12 @@ KernelFn pick_specialized(int unroll, int lanes, int hint) {
 }
 
 KernelFn pick_kernel(int mode, int sig, int unroll, int lanes, int hint) {
-    if (mode == 1) return lanes >= 8 ? raycast_kernel<1, 8, 0, -2> : raycast_kernel<1, 1, 0, -2>;
+    if (mode == 1) {
+        // iso-surface jobs: sig -3 when every source is plain (packed FP32 scalars without
+        // functors, guard layers), else the run-time source handling
+        if (sig == -3) return lanes >= 8 ? raycast_kernel<1, 8, 0, -3> : raycast_kernel<1, 1, 0, -3>;
+        return lanes >= 8 ? raycast_kernel<1, 8, 0, -2> : raycast_kernel<1, 1, 0, -2>;
+    }
     switch (sig) {
     case SIG_F32x1: return pick_specialized<SIG_F32x1>(unroll, lanes, hint);
     case SIG_PIC3_F32: return pick_specialized<SIG_PIC3_F32>(unroll, lanes, hint);
