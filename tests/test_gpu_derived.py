@@ -101,6 +101,28 @@ def test_paired_layout_odd_extents(ctx):
     assert_same(a, b, "odd extents, no guard layers")
 
 
+def test_volume_and_iso_jobs_in_one_call(ctx):
+    """A volume job and an iso job on one volume in the same call share one derived
+    volume, which then keeps x-fastest order (the iso loop reads it); each image
+    equals its direct render."""
+    import torch
+    from paper_1611_09048_amd import DERIVE, DIRECT, device
+    sc = configs.pic3(n=40, width=112, height=80, direction=(0.3, -0.8, 0.5))
+    iso = sc.with_(mode="iso", sources=[dataclasses.replace(s, iso=v) for s, v in
+                                        zip(sc.sources, (1.0, 0.2, float("nan")))])
+    vol = device.upload_volume(ctx, sc, 24)
+    out = {}
+    for flags in (DIRECT, DERIVE):
+        imgs = [device.new_image(sc), device.new_image(iso)]
+        ctx.render([device.render_job(sc, 24, imgs[0]), device.render_job(iso, 24, imgs[1])], flags)
+        torch.cuda.synchronize()
+        out[flags] = [im.cpu().numpy() for im in imgs]
+    for k, label in enumerate(("volume", "iso")):
+        assert np.array_equal(out[DIRECT][k], out[DERIVE][k], equal_nan=True), label
+    log("volume + iso in one call: derived equals direct")
+    del vol
+
+
 def test_derived_iso_mode(ctx):
     sc = configs.pic3(n=40, width=128, height=96)
     sc = sc.with_(mode="iso", sources=[dataclasses.replace(s, iso=v) for s, v in
