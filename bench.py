@@ -672,6 +672,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--jpeg-only", action="store_true",
                     help="only compress the view-0 frame and a noise frame to JPEG (for profiling); prints that result")
+    ap.add_argument("--batch64-only", action="store_true",
+                    help="only the batch of 64 sub-volumes, --steps batches (for profiling); prints that result")
     ap.add_argument("--shape", default="", help="wave_w,waves_x,unroll,lanes,min_waves instead of the tuned shape")
     args = ap.parse_args()
     if args.shape:
@@ -691,6 +693,10 @@ def main():
     ctx = Context(device=0, stream=stream, mem_budget=4 << 30)
     if args.copy_probe:
         log("bench: copy probe", copy_probe(ctx))
+    if args.batch64_only:
+        print(json.dumps(dict(batch64=batch64(ctx, args.steps))), flush=True)
+        ctx.close()
+        return
     log(f"bench: generating pic3 {args.n}^3 {args.dtype} {args.width}x{args.height}")
     sc = configs.pic3(n=args.n, width=args.width, height=args.height, dtype=args.dtype)
     if args.jpeg_only:
