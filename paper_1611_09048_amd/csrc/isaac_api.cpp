@@ -700,7 +700,8 @@ isaac_status enqueue_jobs(isaac_context* ctx, const isaac_render_desc* jobs, con
     la.mode = djs[0].mode;
     if (la.mode == ISAAC_ISO) {
         // the plain-source iso kernel when every source is a packed FP32 scalar without
-        // functors, with guard layers and x-fastest strides (derived volumes, plain scalars)
+        // functors, with guard layers and affine strides (derived volumes in x-fastest
+        // order, plain scalars)
         bool plain = true;
         for (const DevJob& dj : djs)
             for (int k = 0; k < dj.n_src; ++k) {
