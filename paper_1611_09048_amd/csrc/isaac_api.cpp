@@ -313,7 +313,8 @@ isaac_status new_tf_slot(isaac_context* ctx, const float* table, int32_t* handle
         }
     if (slot < 0)
         return set_err(ctx, ISAAC_ERR_OUT_OF_MEMORY, "all %d transfer tables are live; release some", ctx->tf_capacity);
-    // device layout: per entry the value and the difference to the next entry (FP32, as the lookup uses it)
+    // device layout: per entry the value and the difference to the next entry (FP32, as the lookup uses it;
+    // the last entry's difference is 0, and the lookup reads it at the top of the range)
     float rows[kTfRows * 4];
     for (int j = 0; j < kTfEntries; ++j)
         for (int c = 0; c < 4; ++c) {

@@ -225,14 +225,16 @@ __device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], 
 }
 
 // Transfer-table lookup: clamp to [0,1] (NaN -> 0), 255 intervals, linear.
-// No contraction: the fraction is u - j of the rounded u in every caller,
-// whatever the surrounding code lets the compiler fuse.
+// No contraction: the fraction is that of the rounded u in every caller,
+// whatever the surrounding code lets the compiler fuse.  u is in [0, 255], so
+// its fraction is exact and equals u - j; at u = 255 the lookup lands on the
+// last entry, whose slope the table stores as 0, and returns T[255] itself.
 __device__ __forceinline__ float4 classify(const float4* __restrict__ table, float x) {
 #pragma clang fp contract(off)
     float t = fminf(fmaxf(x, 0.f), 1.f);    // max(NaN, 0) = 0
     float u = 255.f * t;
-    int j = min((int)u, 254);
-    float f = u - (float)j;
+    int j = (int)u;
+    float f = __builtin_amdgcn_fractf(u);
     const float4 a = table[2 * j];          // T[j]
     const float4 d = table[2 * j + 1];      // T[j+1] - T[j]
     return make_float4(fmaf(f, d.x, a.x), fmaf(f, d.y, a.y), fmaf(f, d.z, a.z), fmaf(f, d.w, a.w));
