@@ -224,6 +224,31 @@ def test_closed_form_slab_on_gpu(ctx):
         assert np.all(img[~hit] == 0.0)
 
 
+def test_transfer_table_ends_on_gpu(ctx):
+    """Chain outputs at or beyond the ends of [0, 1] classify to the transfer function's end
+    points exactly (a chain maps the data into the transfer function's domain, Sec. 3.3, and
+    outputs outside [0, 1] are clamped to it): a constant
+    source read through add(c) gives 16 identical scan points per ray, so A = 1 - (1 - a)^16
+    and RGB = rgb * A in closed form, with (rgb, a) the first or the last control point."""
+    dims = (8, 6, 5)
+    first, last = (0.0, 0.1, 0.2, 0.3, 0.05), (1.0, 0.7, 0.55, 0.25, 0.08)
+    tf = [first, (0.37, 0.9, 0.1, 0.5, 0.2), last]
+    cam = configs.axis_camera(dims, axis=0, width=9, height=7, ortho_height=9.0)
+    for chain, end in (("add(-41)", last), ("add(-40.3)", last), ("add(-42)", first), ("add(-45)", first)):
+        src = make_source("const42", fields.constant(dims, 0, 42.0), guard=0, chain=chain, tf=tf)
+        for interp in (0, 1):
+            sc = Scene(dims=dims, sources=[src], camera=cam, width=9, height=7, step=0.5, interpolation=interp,
+                       ert_threshold=NO_TERMINATION)
+            img, cnt = gpu_render(ctx, sc)
+            hit = cnt > 0
+            assert np.array_equal(hit, pins._hit_mask(sc)) and np.all(cnt[hit] == 16), chain
+            a = float(np.float32(end[4]))
+            A = 1.0 - (1.0 - a) ** 16
+            assert np.allclose(img[hit][:, 3], A, atol=2e-6), (chain, interp)
+            rgb = np.array(end[1:4], dtype=np.float32).astype(np.float64)
+            assert np.allclose(img[hit][:, :3], rgb * A, atol=2e-6), (chain, interp)
+
+
 def _pic3_variant(sc, **src_changes):
     srcs = [dataclasses.replace(s, **src_changes) for s in sc.sources]
     return sc.with_(sources=srcs)
