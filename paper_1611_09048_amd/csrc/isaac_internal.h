@@ -16,6 +16,11 @@ constexpr int kTfEntries = 256;
 // A table as stored on the device: per entry j two RGBA32F rows, T[j] and
 // T[j+1] - T[j] (the last difference is 0), so a lookup is one FMA per channel.
 constexpr int kTfRows = 2 * kTfEntries;
+// A table as the ray-casting kernels stage it in LDS: the values T[0..255] and
+// a copy of T[255] (the top entry's slope is 0); a lookup forms T[j+1] - T[j] in
+// FP32, the same difference the stored rows hold, so the result is unchanged
+// while a workgroup's tables take half the LDS.
+constexpr int kTfLds = kTfEntries + 1;
 constexpr int kMaxBatch = 256;
 constexpr int kBlockThreads = 256;     // 4 waves of 64
 

@@ -224,20 +224,22 @@ __device__ __forceinline__ void run_chain(const DevSource& S, float (&v)[N][4], 
     }
 }
 
-// Transfer-table lookup: clamp to [0,1] (NaN -> 0), 255 intervals, linear.
-// No contraction: the fraction is that of the rounded u in every caller,
-// whatever the surrounding code lets the compiler fuse.  u is in [0, 255], so
-// its fraction is exact and equals u - j; at u = 255 the lookup lands on the
-// last entry, whose slope the table stores as 0, and returns T[255] itself.
+// Transfer-table lookup in a staged table (kTfLds values): clamp to [0,1]
+// (NaN -> 0), 255 intervals, linear.  No contraction: the fraction is that of
+// the rounded u in every caller, whatever the surrounding code lets the
+// compiler fuse.  u is in [0, 255], so its fraction is exact and equals u - j;
+// at u = 255 the lookup lands on the last entry, whose copy makes the slope 0,
+// and returns T[255] itself.
 __device__ __forceinline__ float4 classify(const float4* __restrict__ table, float x) {
 #pragma clang fp contract(off)
     float t = fminf(fmaxf(x, 0.f), 1.f);    // max(NaN, 0) = 0
     float u = 255.f * t;
     int j = (int)u;
     float f = __builtin_amdgcn_fractf(u);
-    const float4 a = table[2 * j];          // T[j]
-    const float4 d = table[2 * j + 1];      // T[j+1] - T[j]
-    return make_float4(fmaf(f, d.x, a.x), fmaf(f, d.y, a.y), fmaf(f, d.z, a.z), fmaf(f, d.w, a.w));
+    const float4 a = table[j];              // T[j]
+    const float4 b = table[j + 1];          // T[j+1]
+    return make_float4(fmaf(f, b.x - a.x, a.x), fmaf(f, b.y - a.y, a.y), fmaf(f, b.z - a.z, a.z),
+                       fmaf(f, b.w - a.w, a.w));
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
@@ -620,7 +622,7 @@ __device__ __forceinline__ void point_generic(const DevJob& J, const float4* __r
     for (int s = 0; s < J.n_src; ++s) {
         const DevSource& src = J.src[s];
         const float x = sample_source<INTERP>(src, dims, p);
-        const float4 c = classify(s_tf + s * kTfRows, x);
+        const float4 c = classify(s_tf + s * kTfLds, x);
         const float wa = src.weight * c.w;
         S = fmaf(src.weight, c.w, S);
         E[0] = fmaf(wa, c.x, E[0]);
@@ -679,7 +681,7 @@ __device__ __forceinline__ void points(const DevJob& J, const float4* __restrict
             E[u][0] = E[u][1] = E[u][2] = 0.f;
         }
         auto accumulate = [&](int u, int s, float x) {
-            const float4 cl = classify(s_tf + s * kTfRows, x);
+            const float4 cl = classify(s_tf + s * kTfLds, x);
             const float wa = J.src[s].weight * cl.w;
             S[u] = fmaf(J.src[s].weight, cl.w, S[u]);
             E[u][0] = fmaf(wa, cl.x, E[u][0]);
@@ -918,7 +920,7 @@ __device__ __forceinline__ void il3_mix(const DevJob& J, const float4* __restric
         float c[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) c[i] = v[i][s];
-        const float4 cl = classify(s_tf + s * kTfRows, blend<NV>(c, w));
+        const float4 cl = classify(s_tf + s * kTfLds, blend<NV>(c, w));
         const float wa = J.src[s].weight * cl.w;
         S = fmaf(J.src[s].weight, cl.w, S);
         E[0] = fmaf(wa, cl.x, E[0]);
@@ -1037,7 +1039,7 @@ __device__ __forceinline__ float4 iso_shade(const DevJob& J, const float4* __res
     const float gl = sqrtf(fmaf(g[0], g[0], fmaf(g[1], g[1], g[2] * g[2])));
     const float cosine = gl > 0.f ? fabsf(fmaf(g[0], R.d[0], fmaf(g[1], R.d[1], g[2] * R.d[2]))) / gl : 1.f;
     const float light = fmaf(0.7f, fminf(cosine, 1.f), 0.3f);
-    const float4 c = classify(s_tf + s * kTfRows, S.iso);
+    const float4 c = classify(s_tf + s * kTfLds, S.iso);
     return make_float4(c.x * light, c.y * light, c.z * light, 1.f);
 }
 
@@ -1207,10 +1209,10 @@ void raycast_kernel(const DevJob* __restrict__ jobs, const float4* __restrict__ 
         // tiles no ray of which meets the box skip the transfer tables; the
         // barrier also ends every read of the previous tile's tables
         if (__syncthreads_or(hit) && job != cur_job) {
-            const int n = J.n_src * kTfRows;
+            const int n = J.n_src * kTfLds;
             for (int i = threadIdx.x; i < n; i += kBlockThreads) {
-                const int s = i / kTfRows, e = i % kTfRows;
-                s_tf[i] = tf_pool[(size_t)J.src[s].tf_slot * kTfRows + e];
+                const int s = i / kTfLds, e = min(i % kTfLds, kTfEntries - 1);
+                s_tf[i] = tf_pool[(size_t)J.src[s].tf_slot * kTfRows + 2 * e];
             }
             __syncthreads();
             cur_job = job;
@@ -1315,9 +1317,9 @@ void raycast_pool_kernel(const DevJob* __restrict__ jobs, const float4* __restri
     extern __shared__ float4 s_tf[];
     const DevJob& J = jobs[0];
     {
-        const int n = J.n_src * kTfRows;
+        const int n = J.n_src * kTfLds;
         for (int i = (int)threadIdx.x; i < n; i += kBlockThreads)
-            s_tf[i] = tf_pool[(size_t)J.src[i / kTfRows].tf_slot * kTfRows + i % kTfRows];
+            s_tf[i] = tf_pool[(size_t)J.src[i / kTfLds].tf_slot * kTfRows + 2 * min(i % kTfLds, kTfEntries - 1)];
         __syncthreads();
     }
     const int n_rays = __builtin_amdgcn_readfirstlane(counters[0]);   // the setup kernel's count
@@ -1832,8 +1834,8 @@ int launch_prepass_one(const DevJob& job, DevJob* dst, unsigned fill_blocks, int
 }
 
 int launch_raycast(const LaunchArgs& a, void* stream) {
-    // dynamic LDS: one 256-entry RGBA32F table per active source of the widest job
-    const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfRows * sizeof(float4);
+    // dynamic LDS: one staged table (kTfLds RGBA32F values) per active source of the widest job
+    const size_t lds = (size_t)(a.max_src > 0 ? a.max_src : 1) * kTfLds * sizeof(float4);
     const unsigned blocks = a.persistent ? (unsigned)a.grid : (unsigned)a.total_tiles;
     if (blocks == 0) return hipGetLastError();
     const KernelFn kernel = pick_kernel(a.mode, a.sig, a.unroll, a.lanes, a.waves_hint);
@@ -1878,7 +1880,7 @@ int launch_raycast_pooled(const DevJob* job_dev, int width, int height, const fl
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counters, 2);
     const dim3 sgrid((unsigned)((width + 15) / 16), (unsigned)((height + 15) / 16));
     hipLaunchKernelGGL(ray_setup_kernel, sgrid, dim3(256), 0, st, job_dev, static_cast<RayRec*>(rays), counters);
-    const size_t lds = (size_t)(max_src > 0 ? max_src : 1) * kTfRows * sizeof(float4);
+    const size_t lds = (size_t)(max_src > 0 ? max_src : 1) * kTfLds * sizeof(float4);
     const PoolFn k = pick_pool_kernel(sig, lanes, hint);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlockThreads, lds) != hipSuccess || per_cu < 1)
@@ -1996,7 +1998,7 @@ int noalloc_scratch(int device, void** ptr) {
 
 int raycast_occupancy(int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, raycast_kernel<1, 1, 0, -1>, kBlockThreads,
-                                                       3 * kTfRows * sizeof(float4));
+                                                       3 * kTfLds * sizeof(float4));
 }
 
 }  // namespace isaac
