@@ -848,6 +848,11 @@ __device__ __forceinline__ void group_scan(int lane, float& c0, float& c1, float
     }
 }
 
+// One row of G scan points of a ray composited into acc.  A lane past the ray's
+// last scan point (valid false) may carry any finite values (the callers give it
+// the last point's sample): the scan is inclusive, so no kept lane's prefix
+// depends on it, the termination ballot masks it, and the lane taken is never
+// past the row's last kept point.
 template <int G>
 __device__ __forceinline__ bool row_composite(const DevJob& J, const RaySetup& R, int lane, int k0, bool valid,
                                               float c0, float c1, float c2, float a, RayAccum& acc) {
@@ -882,8 +887,7 @@ __device__ __forceinline__ bool lanes_row(const DevJob& J, const float4* __restr
     const bool valid = k < R.ke;
     float E[1][3], S[1];
     points<INTERP, 1, SIG, PS>(J, s_tf, R, valid ? k : R.ke - 1, E, S);
-    return row_composite<G>(J, R, lane, k0, valid, valid ? E[0][0] : 0.f, valid ? E[0][1] : 0.f,
-                            valid ? E[0][2] : 0.f, valid ? S[0] : 0.f, acc);
+    return row_composite<G>(J, R, lane, k0, valid, E[0][0], E[0][1], E[0][2], S[0], acc);
 }
 
 // Interleaved derived volume (SIG_IL3), G lanes per ray, software-pipelined:
@@ -949,8 +953,7 @@ __device__ __forceinline__ void march_lanes_il3(const DevJob& J, const float4* _
         const bool valid = k0 + g < R.ke;
         float E[3], S;
         il3_mix<NV>(J, s_tf, v, w, E, S);
-        if (row_composite<G>(J, R, lane, k0, valid, valid ? E[0] : 0.f, valid ? E[1] : 0.f, valid ? E[2] : 0.f,
-                             valid ? S : 0.f, acc))
+        if (row_composite<G>(J, R, lane, k0, valid, E[0], E[1], E[2], S, acc))
             break;
 #pragma unroll
         for (int i = 0; i < NV; ++i)
