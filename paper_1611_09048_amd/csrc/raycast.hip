@@ -1646,12 +1646,14 @@ __device__ __forceinline__ void derive_voxels(const DeriveArgs& a, int xi, int s
 
 // Blocks of 256 threads cover consecutive threads of consecutive rows (y, or
 // stored y pairs of 2 ex threads) of one slab (4 z-slices, or 2 stored z
-// pairs); grid z strides over the slabs.  Eight waves per SIMD: left to
-// itself the compiler keeps the arguments in up to 106 scalar registers,
-// which leaves room for seven, and this latency-bound pass runs faster with
-// the eighth wave's loads in flight.
+// pairs); grid z strides over the slabs.  Eight waves per SIMD for the paired
+// signature-specialized variants: left to itself the compiler keeps the
+// arguments in up to 106 scalar registers, which leaves room for seven, and
+// this latency-bound pass runs faster with the eighth wave's loads in flight
+// (the other variants would spill to scratch under that bound: no bound).
 template <int SIG, bool PAIRED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void derive_kernel(DeriveArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAIRED && SIG != SIG_GENERIC ? 8 : 1, 8)))
+void derive_kernel(DeriveArgs a) {
     const int ex = a.ext[0];
     const int row = PAIRED ? 2 * ex : ex;
     const int rows = PAIRED ? a.ny2 : a.ext[1];
