@@ -73,6 +73,49 @@ def test_batch_equals_alone_bitwise(ctx):
     del vols
 
 
+def test_batch_of_maximum_size(ctx):
+    """256 jobs (the most one call takes) on two volumes, each with its own camera and ragged
+    image size, in one call: every job equals the same job rendered alone, bit for bit, with
+    the graph and without; a sample of them also matches the oracle."""
+    import torch
+    from paper_1611_09048_amd import NO_GRAPH, binding, device
+    assert binding.MAX_BATCH == 256
+    bases = [configs.pic3(n=20, width=24, height=16), configs.plain_scalar(n=18, width=24, height=16)]
+    vols = [device.upload_volume(ctx, sc, vid) for vid, sc in enumerate(bases)]
+    views = configs.views26()
+    scenes_, jobs, imgs, cnts = [], [], [], []
+    for k in range(binding.MAX_BATCH):
+        vid = k % 2
+        base = bases[vid]
+        sc = base.with_(camera=configs.orbit_camera(base.dims, views[k % 26], distance_factor=0.9 + 0.002 * k),
+                        width=17 + k % 13, height=11 + k % 7)
+        scenes_.append(sc)
+        imgs.append(device.new_image(sc))
+        cnts.append(device.new_counts(sc))
+        jobs.append(device.render_job(sc, vid, imgs[-1], cnts[-1]))
+    torch.cuda.synchronize()
+    alone = []
+    for j, img, cnt in zip(jobs, imgs, cnts):
+        ctx.render([j])
+        torch.cuda.synchronize()
+        alone.append((img.clone(), cnt.clone()))
+    assert sum(int((a[1] > 0).sum()) for a in alone) > 5000, "the jobs should see the volumes"
+    for mode, flags in (("graph", 0), ("direct", NO_GRAPH)):
+        for img, cnt in zip(imgs, cnts):
+            img.fill_(float("nan"))
+            cnt.fill_(-7)
+        ctx.render(jobs, flags)
+        torch.cuda.synchronize()
+        for k, (img, cnt) in enumerate(zip(imgs, cnts)):
+            assert torch.equal(img, alone[k][0]), (mode, k)
+            assert torch.equal(cnt, alone[k][1]), (mode, k)
+    for k in (0, 1, 77, 128, 254, 255):
+        rec = oracle.render(scenes_[k])
+        compare(imgs[k].cpu().numpy().reshape(-1, 4), cnts[k].cpu().numpy().reshape(-1), rec,
+                label=f"batch of 256: job {k}")
+    del vols
+
+
 def test_batch_jobs_match_oracle(ctx):
     import torch
     scenes_ = _mixed_scenes()

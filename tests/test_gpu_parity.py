@@ -249,6 +249,51 @@ def test_transfer_table_ends_on_gpu(ctx):
             assert np.allclose(img[hit][:, :3], rgb * A, atol=2e-6), (chain, interp)
 
 
+# Chains of exactly 8 functors (the interface's maximum) for sources of 1 to 4 components.
+_MAX_CHAINS = {
+    1: "mul(1.5) | add(0.25) | pow(2) | mul(0.5) | add(-0.125) | mul(2) | add(0.1) | mul(0.75)",
+    2: "mul(0.5, 1.5) | add(0.25) | pow(2) | add(-0.1, 0.2) | mul(1.25) | sum | mul(0.5) | add(0.05)",
+    3: "mul(2, 3, 4) | add(1) | mul(0.1) | pow(2) | add(-0.2, 0.1, 0) | length | mul(0.6) | add(-0.05)",
+    4: "add(0.5) | mul(0.25, 0.5, 0.75, 1) | pow(2) | add(0.1) | mul(1.5) | sum | mul(0.2) | pow(0.5)",
+}
+
+
+def _maximum_scene(interpolation):
+    """8 sources (1 to 4 components, FP32/FP16/BF16, AoS and SoA, with and without guard
+    layers), each behind an 8-functor chain, and 8 clipping planes: every per-render limit
+    of the interface at once (Sec. 3.2 sources, Sec. 3.3 chains)."""
+    rng = np.random.default_rng(811)
+    dims = (14, 12, 10)
+    srcs = []
+    for s in range(8):
+        f_dim = 1 + s % 4
+        guard = s % 2
+        vals = fields.uniform_random(rng, dims, guard, f_dim, -1.0, 1.5)
+        srcs.append(make_source(f"s{s}", vals, dtype=("f32", "f16", "bf16")[s % 3], guard=guard,
+                                chain=_MAX_CHAINS[f_dim], weight=float(rng.uniform(0.2, 1.0)),
+                                tf=configs.random_tf(rng, 5, 0.3), layout=("aos", "soa")[(s // 2) % 2]))
+    # 8 planes, each keeping the side of the centre within 0.3 of the box diagonal along a
+    # random normal: every plane cuts, and a region around the centre stays
+    c = np.array(dims, dtype=np.float64) / 2.0
+    r = 0.3 * float(np.linalg.norm(dims))
+    clip = []
+    for _ in range(8):
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        clip.append((float(-n[0]), float(-n[1]), float(-n[2]), float(n @ c + r)))
+    cam = configs.orbit_camera(dims, (0.3, -0.8, 0.5))
+    return Scene(dims=dims, sources=srcs, camera=cam, width=96, height=72, step=0.5,
+                 interpolation=interpolation, clip=clip, ert_threshold=0.999, label=f"maximums interp={interpolation}")
+
+
+@pytest.mark.parametrize("interpolation", [0, 1])
+def test_interface_maximums(ctx, interpolation):
+    """Every pixel and sample count against the oracle at the interface's per-render maximums."""
+    sc = _maximum_scene(interpolation)
+    img, cnt, rec = full_parity(ctx, sc, sc.label, max_flagged=0.05)
+    assert (cnt > 0).sum() > 200, "the clipped volume should still cover some pixels"
+
+
 def _pic3_variant(sc, **src_changes):
     srcs = [dataclasses.replace(s, **src_changes) for s in sc.sources]
     return sc.with_(sources=srcs)
