@@ -443,6 +443,54 @@ def test_tiny_and_ragged_images(ctx):
         compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=f"ragged {w}x{h}")
 
 
+def _degenerate_scenes():
+    """(label, scene, expect_empty) for the method's degenerate inputs."""
+    rng = np.random.default_rng(97)
+    out = []
+    for dims in ((1, 9, 7), (13, 1, 1), (6, 5, 1), (1, 1, 1)):
+        for guard in (0, 1):
+            vals = fields.uniform_random(rng, dims, guard, 3, -1.0, 1.5)
+            src = make_source("v", vals, guard=guard, chain="length | mul(0.7)", weight=1.0,
+                              tf=configs.random_tf(rng, 4, 0.6))
+            for interp in (0, 1):
+                cam = configs.orbit_camera(dims, (0.4, -0.7, 0.6), distance_factor=2.5)
+                out.append((f"thin {dims} guard={guard} interp={interp}",
+                            Scene(dims=dims, sources=[src], camera=cam, width=21, height=17, step=0.5,
+                                  interpolation=interp), False))
+    base = configs.pic3(n=16, width=40, height=30)
+    c = np.array(base.dims, dtype=np.float64) / 2.0
+    # two opposite planes whose kept sides do not meet: nothing is kept
+    out.append(("clipped away", base.with_(clip=[(1.0, 0.0, 0.0, -(c[0] + 3.0)), (-1.0, 0.0, 0.0, c[0] - 3.0)]),
+                True))
+    # a camera whose view points away from the box
+    away = configs.orbit_camera(base.dims, (0.3, 0.5, -0.8))
+    back = dataclasses.replace(away, center=tuple(2.0 * np.array(away.eye) - np.array(away.center)))
+    out.append(("looking away", base.with_(camera=back), True))
+    out.append(("termination threshold 1e-6", base.with_(ert_threshold=1e-6), False))
+    out.append(("step longer than the box", base.with_(step=40.0), False))
+    return out
+
+
+def test_degenerate_inputs(ctx):
+    """Volumes one cell thick (and a single cell), with and without guard layers; clip planes
+    that keep nothing; a camera looking away from the box; a termination threshold of 1e-6
+    (a ray ends at its first scan point of any opacity); a step longer than the box (at most one
+    scan point): every pixel and sample count against the oracle, and the empty cases empty.
+    A threshold of 0 is the interface's default, 0.999: the same image bit for bit."""
+    base = configs.pic3(n=16, width=40, height=30)
+    d0, c0 = gpu_render(ctx, base.with_(ert_threshold=0.0))
+    d1, c1 = gpu_render(ctx, base.with_(ert_threshold=0.999))
+    assert np.array_equal(d0, d1) and np.array_equal(c0, c1)
+    for label, sc, empty in _degenerate_scenes():
+        img, cnt = gpu_render(ctx, sc)
+        rec = oracle.render(sc)
+        compare(img.reshape(-1, 4), cnt.reshape(-1), rec, label=label)
+        if empty:
+            assert np.all(cnt == 0) and np.all(img == 0.0), label
+        else:
+            assert (cnt > 0).any(), label
+
+
 def test_mirror_symmetry(ctx):
     """A field mirror-symmetric in y seen from the mirror plane gives a left-right mirrored image."""
     rng = np.random.default_rng(5)
